@@ -1,0 +1,210 @@
+"""Benchmark: STTSV hyperedges/s on one MI355X, plus the H-eigenvector solve.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (default): the Zipf / power-law hypergraph, n = 1e6 vertices,
+m = 5e6 edges, sizes P(k) ~ k^-2.5 on [2, 25], tensor order r = 25, Zipf(1.0)
+membership, x uniform on (0, 1] -- seeded synthetic data.  A step is one full
+STTSV y = B x^(r-1) (every edge-kernel launch plus the node reduction) with
+x and y resident in HBM.  Prints one JSON line.
+"""
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_FP64_VALU = 78.6e12   # FLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_FP32_VALU = 157.3e12  # FLOP/s published (needs packed FP32, which this build disables)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def edge_fma(k, r):
+    """Series FMAs of one edge of size k at order r, as the kernels compute
+    them: truncated products W(W-1)/2 each, dot products of W terms."""
+    W = r - k + 1
+    prod = W * (W - 1) // 2
+    if k == 1:
+        return 0
+    if k == 2:
+        return max(W - 1, 0)
+    if k == 3:
+        return 2 * W + prod + max(W - 1, 0)
+    return 2 * (k - 3) * prod + (k + 1) * W - 1
+
+
+def edge_bytes(k):
+    """Algorithmic HBM bytes of one edge: member ids (4k), gathered x (8k),
+    contributions written (8k)."""
+    return 20 * k
+
+
+def stage_table(plan, xd, yd, prec, reps):
+    from paper_2311_08595_amd import _lib
+    lib = _lib.load()
+    cap = 256
+    ns = ctypes.c_int32()
+    kinds = (ctypes.c_int32 * cap)()
+    sizes = (ctypes.c_int32 * cap)()
+    counts = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_float * cap)()
+    acc = None
+    for _ in range(reps):
+        _lib.check(lib.sttsv_apply_timed(plan._h, ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                                         _lib.PREC[prec], cap, ctypes.byref(ns), kinds, sizes, counts, ms))
+        cur = np.array(ms[:ns.value], dtype=np.float64)
+        acc = cur if acc is None else acc + cur
+    acc /= reps
+    return [dict(kind=int(kinds[i]), size=int(sizes[i]), count=int(counts[i]), ms=float(acc[i]))
+            for i in range(ns.value)]
+
+
+def roofline_of(stages, r, prec):
+    """Dominant stage and its roofline figures."""
+    best = max(stages, key=lambda s: s["ms"])
+    t = best["ms"] * 1e-3
+    if best["kind"] == 0:
+        k, m = best["size"], best["count"]
+        flops = 2.0 * edge_fma(k, r) * m
+        byts = edge_bytes(k) * m
+        peak_f = PEAK_FP64_VALU if prec == "fp64" else PEAK_FP64_VALU  # non-packed FP32 = FP64 rate
+        if flops / peak_f >= byts / PEAK_HBM:
+            return best, dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
+                              frac=(flops / t) / peak_f, traffic=None,
+                              kernel="edge k=%d (W=%d), %d edges" % (k, r - k + 1, m))
+        return best, dict(bound="hbm", achieved=byts / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                          frac=(byts / t) / PEAK_HBM, traffic=None,
+                          kernel="edge k=%d (W=%d), %d edges" % (k, r - k + 1, m))
+    return best, dict(bound="hbm", achieved=None, peak=PEAK_HBM / 1e9, unit="GB/s", frac=None,
+                      traffic=None, kernel="reduce level %d" % best["size"])
+
+
+def cpu_baseline(w, sample_edges, seed=0):
+    from oracle import sttsv_ref
+    rng = np.random.default_rng(seed)
+    m = len(w["eptr"]) - 1
+    pick = np.sort(rng.choice(m, size=min(sample_edges, m), replace=False))
+    sizes = np.diff(w["eptr"])[pick]
+    eptr = np.zeros(len(pick) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=eptr[1:])
+    src = np.repeat(w["eptr"][pick], sizes) + (np.arange(eptr[-1]) - np.repeat(eptr[:-1], sizes))
+    eidx = w["eidx"][src]
+    t0 = time.perf_counter()
+    sttsv_ref.sttsv(eptr, eidx, w["n"], w["r"], w["x"])
+    dt = time.perf_counter() - t0
+    return dict(value=len(pick) / dt, unit="hyperedges/s", cores=1, kind="oracle",
+                sample="%d random edges of the same hypergraph (all n=%d vertices), one process, "
+                       "numpy FP64 AAY + fsum; %.1f s" % (len(pick), w["n"], dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--m", type=int, default=5_000_000)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-edges", type=int, default=300000)
+    ap.add_argument("--stage-reps", type=int, default=5)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the STTSV path is built and measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    log("[bench] generating workload")
+    w = wl.zipf_powerlaw(n=a.n, m=a.m)
+    n, r, m = w["n"], w["r"], len(w["eptr"]) - 1
+    log("[bench] planning n=%d m=%d nnz=%d r=%d" % (n, m, len(w["eidx"]), r))
+    t0 = time.perf_counter()
+    plan = st.Plan(w["eptr"], w["eidx"], n, r)
+    plan_s = time.perf_counter() - t0
+    xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+    yd = torch.empty_like(xd)
+
+    res = {}
+    for prec in ("fp64", "fp32"):
+        log("[bench] timing STTSV %s" % prec)
+        for _ in range(a.warmup):
+            plan.apply(xd, yd, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            plan.apply(xd, yd, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        stages = stage_table(plan, xd, yd, prec, a.stage_reps)
+        res[prec] = dict(ms=dt * 1e3, stages=stages)
+        log("[bench]   %s: %.3f ms/STTSV, %.3e hyperedges/s" % (prec, dt * 1e3, m / dt))
+
+    out = {
+        "metric": "STTSV hyperedges/s",
+        "value": m / (res["fp64"]["ms"] * 1e-3),
+        "unit": "hyperedges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": res["fp64"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n": n, "m": m, "nnz": int(len(w["eidx"])), "r": r,
+                   "sizes": "P(k)~k^-2.5 on [2,25]", "membership": "Zipf(1.0)",
+                   "parallelism": "1 GPU"},
+    }
+    best, roof = roofline_of(res["fp64"]["stages"], r, "fp64")
+    roof["avg_kernel_ms"] = best["ms"]
+    out["roofline"] = roof
+    best32, roof32 = roofline_of(res["fp32"]["stages"], r, "fp32")
+    roof32["avg_kernel_ms"] = best32["ms"]
+    out["fp32_series"] = {"value": m / (res["fp32"]["ms"] * 1e-3), "ms_per_step": res["fp32"]["ms"],
+                          "roofline": roof32}
+    out["stages_fp64_ms"] = [(s["kind"], s["size"], s["count"], round(s["ms"], 5)) for s in res["fp64"]["stages"]]
+    out["stages_fp32_ms"] = [(s["kind"], s["size"], s["count"], round(s["ms"], 5)) for s in res["fp32"]["stages"]]
+    out["plan_s"] = plan_s
+    plan.close()
+
+    if not a.no_solve:
+        log("[bench] largest component + solves")
+        e2, i2, n2, _ = wl.largest_component(w["eptr"], w["eidx"], n)
+        with st.Plan(e2, i2, n2, r) as p2:
+            solve = {"n_lcc": n2, "m_lcc": len(e2) - 1, "tol": 1e-8}
+            for sched in ("fp64", "fp32_fp64"):
+                p2.solve(tol=1e-8, schedule=sched)           # warm-up (graph capture)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = p2.solve(tol=1e-8, schedule=sched)
+                dt = time.perf_counter() - t0
+                solve[sched] = dict(seconds=dt, iterations=info["iterations"], iters_fp32=info["iters_fp32"],
+                                    iters_fp64=info["iters_fp64"], lambda_max=info["lambda_max"],
+                                    criterion=info["criterion"])
+                log("[bench]   solve %s: %.4f s, %d iterations" % (sched, dt, info["iterations"]))
+        out["solve"] = solve
+    if not a.no_cpu:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edges)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * sttsv.h -- C ABI of the MI355X STTSV library.
+ *
+ * STTSV (sparse symmetric tensor times same vector, TTSV1 of Eq. (1)-(2))
+ * on the order-r blowup adjacency tensor B of a non-uniform hypergraph
+ * H = (V, E) (Sec. II), and the NQZ iteration for H-eigenvector centrality
+ * that calls it on every step (Alg. 1).
+ *
+ *   B: for every edge e and every r-tuple i whose entry set is exactly e,
+ *      B_i = w(e)/|beta(e)|, |beta(e)| = |e|! S(r,|e|), w(e) = |e| (Sec. II
+ *      and its footnote), so that B 1^(r-1) = vertex degrees.
+ *   y = B x^(r-1):  y_v = sum_{i2..ir} B_{v,i2..ir} x_{i2} ... x_{ir}  (Eq. (2)),
+ *      evaluated per (edge, member) with the generating-function form of
+ *      Alg. 2 (Sec. II-A), never enumerating the blowup entries.
+ *
+ * Conventions
+ *   - Every call returns an int: STTSV_OK (0) or a negative STTSV_E* code.
+ *     No exception crosses the ABI.  sttsv_strerror() names a code.
+ *   - Vertex ids are 0-based int32 (the paper counts from 1); edge offsets are
+ *     int64.  A hypergraph is passed as CSR: edge i is
+ *     eidx[eptr[i] .. eptr[i+1]-1].
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory (e.g. from torch on a ROCm build).  Device work is
+ *     ordered on the plan's stream (sttsv_opts.stream, default stream if
+ *     NULL) and is asynchronous unless stated otherwise.
+ *   - The library owns every buffer it allocates; callers own what they pass.
+ */
+#ifndef STTSV_H
+#define STTSV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define STTSV_OK              0
+#define STTSV_EINVAL         -1  /* invalid argument or malformed hypergraph        */
+#define STTSV_ENOMEM         -2  /* host or device allocation failed                */
+#define STTSV_EDISCONNECTED  -3  /* solver needs a connected hypergraph (Sec. II)   */
+#define STTSV_ENOTCONV       -4  /* solver hit max_iter; partial result returned    */
+#define STTSV_ENUMERIC       -5  /* NaN / Inf / non-positive value met in the solve */
+#define STTSV_EHIP           -6  /* a HIP runtime call failed                       */
+#define STTSV_ENOTSUP        -7  /* request outside the supported range             */
+
+#define STTSV_MAX_ORDER      64  /* largest supported tensor order r                */
+
+/* ---- precision of the series arithmetic ------------------------------- */
+#define STTSV_PREC_FP64       0  /* series, weights, sums all in FP64               */
+#define STTSV_PREC_FP32       1  /* series in FP32 (FMA), weights / products /      */
+                                 /* per-vertex sums in FP64                         */
+
+typedef struct sttsv_plan_s* sttsv_plan_t;
+
+/* Options for sttsv_plan.  Pass NULL for all defaults. */
+typedef struct {
+    int32_t precision;   /* STTSV_PREC_FP64 (default) or STTSV_PREC_FP32        */
+    int32_t reserved0;
+    void*   stream;      /* hipStream_t the plan's work is ordered on; NULL =   */
+                         /* the default stream                                   */
+} sttsv_opts;
+
+/*
+ * sttsv_plan -- build an execution plan for the hypergraph (host CSR).
+ *
+ *   eptr  host, int64[m+1]: edge offsets, eptr[0] = 0, strictly increasing
+ *         (every edge non-empty), eptr[m] = nnz.
+ *   eidx  host, int32[nnz]: member vertex ids in [0, n); no vertex twice
+ *         in one edge (E is a set system, Sec. II).  Member order and edge
+ *         order are free; a repeated edge counts once per copy.
+ *   m     number of edges (>= 1);  n  number of vertices (>= 1);
+ *   r     tensor order, 2 <= r <= STTSV_MAX_ORDER, r >= max |e| (the blowup
+ *         tensor may be of higher order than the rank of H).
+ *   opts  host, nullable.
+ *   out   host: receives the plan handle on success; untouched on error.
+ *
+ * The arrays are copied; the caller may free them on return.  The plan
+ * holds all device buffers (member layout, per-incidence contributions,
+ * node-major incidence lists, reduction schedule, weight table
+ * w(e)/|beta(e)| (r-1)! per edge size).  Blocking (uploads are synchronous).
+ * Errors: EINVAL (malformed input), ENOTSUP (r out of range), ENOMEM, EHIP.
+ */
+int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n,
+               int32_t r, const sttsv_opts* opts, sttsv_plan_t* out);
+
+/*
+ * sttsv_apply -- y = B x^(r-1)  (TTSV1, Eq. (2); Alg. 2 per edge and member).
+ *
+ *   x  device, double[n], read only (any finite values; accuracy statements
+ *      hold for x >= 0, where every term is non-negative).
+ *   y  device, double[n], fully overwritten (isolated vertices get 0).
+ *      Must not alias x.
+ *
+ * Uses the plan's precision and stream; asynchronous.  The result is
+ * bitwise reproducible: each y_v is summed in a fixed order that depends only
+ * on the hypergraph, never on launch timing (no floating-point atomics).
+ * Errors: EINVAL (NULL arguments), EHIP (launch failure).
+ */
+int sttsv_apply(sttsv_plan_t plan, const double* x, double* y);
+
+/* As sttsv_apply with an explicit precision (STTSV_PREC_*). */
+int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t precision);
+
+/*
+ * sttsv_apply_timed -- sttsv_apply_prec, with every stage timed by a pair of
+ * hipEvents recorded on the plan's stream (for measurement tools).
+ *
+ * Stage s is either the edge-kernel launch of one size bucket
+ * (kinds[s] = 0, sizes[s] = edge size k, counts[s] = edges in the bucket) or
+ * one level of the node reduction (kinds[s] = 1, sizes[s] = level,
+ * counts[s] = chunks).  ms[s] = elapsed milliseconds of that stage.
+ *   cap      capacity of the four host output arrays (entries)
+ *   nstages  host: number of stages (set even when cap is too small, then
+ *            EINVAL is returned and nothing is launched)
+ * Synchronous (waits for the stream).  Same result as sttsv_apply_prec.
+ */
+int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t precision,
+                      int32_t cap, int32_t* nstages, int32_t* kinds, int32_t* sizes,
+                      int64_t* counts, float* ms);
+
+/* ---- H-eigenvector centrality (Alg. 1) ------------------------------- */
+
+/* Precision schedules of the solver. */
+#define STTSV_SOLVE_FP64       0  /* every STTSV in FP64 series                       */
+#define STTSV_SOLVE_FP32_FP64  1  /* FP32-series iterations until the criterion      */
+                                  /* stops improving or falls below switch_tol, then */
+                                  /* FP64-series iterations until it is < tol        */
+
+typedef struct {
+    int32_t max_iter;      /* default 500                                       */
+    int32_t check_every;   /* iterations per graph replay between host checks  */
+                           /* of the convergence flag (default 8)               */
+    int32_t schedule;      /* STTSV_SOLVE_* (default FP64)                       */
+    int32_t use_graph;     /* 1 (default): replay a captured hipGraph           */
+    double  shift;         /* alpha >= 0: z <- z + alpha x^[r-1] (default 0)    */
+    double  switch_tol;    /* FP32->FP64 switch threshold (default 1e-6)        */
+} sttsv_solve_opts;
+
+typedef struct {
+    int32_t iterations;    /* repeat-loop passes of Alg. 1                      */
+    int32_t iters_fp32;    /* of which with FP32 series                         */
+    int32_t iters_fp64;    /* of which with FP64 series                         */
+    int32_t converged;     /* 1 if criterion < tol                              */
+    double  lambda_min;    /* min_v z_v / x_v^(r-1) at the returned x           */
+    double  lambda_max;    /* max_v z_v / x_v^(r-1) at the returned x           */
+    double  criterion;     /* (lambda_max - lambda_min) / lambda_min            */
+} sttsv_solve_info;
+
+/*
+ * heigvec_solve -- NQZ iteration (Alg. 1) for the H-eigenvector centrality x:
+ * positive x with B x^(r-1) = lambda x^[r-1] (Sec. II).
+ *
+ *   x0     device, double[n] or NULL.  NULL = the uniform start 1/n of
+ *          Alg. 1; otherwise a warm start, entrywise > 0 and finite.
+ *   tol    tau > 0: stop when (lambda_max - lambda_min)/lambda_min < tau.
+ *   x_out  device, double[n]: the iterate whose TTSV1 met the test,
+ *          normalised to ||x||_1 = 1 (Alg. 1).  May alias x0.
+ *   info   host, nullable: iteration counts and the final eigenvalue bounds.
+ *
+ * Requires a connected hypergraph with no isolated vertex (the
+ * Perron-Frobenius condition stated in Sec. II): else EDISCONNECTED.
+ * ENOTCONV if max_iter passes did not meet tol (x_out and info then hold the
+ * last iterate); ENUMERIC if a non-finite or non-positive value appears;
+ * EINVAL for a bad x0 or tol.  Synchronises the plan's stream.
+ */
+int heigvec_solve(sttsv_plan_t plan, const double* x0, double tol, double* x_out,
+                  sttsv_solve_info* info);
+
+/* As heigvec_solve with options (opts host, nullable = defaults). */
+int heigvec_solve_ex(sttsv_plan_t plan, const double* x0, double tol,
+                     const sttsv_solve_opts* opts, double* x_out,
+                     sttsv_solve_info* info);
+
+/* ---- plan introspection (host copies; used to check the layout) ------- */
+#define STTSV_Q_PERM        0  /* int64[m]   input index of canonical edge c      */
+#define STTSV_Q_MEM         1  /* int64[nnz] member slots (original vertex ids)   */
+#define STTSV_Q_BUCKET_K    2  /* int64[nb]  edge size of each bucket             */
+#define STTSV_Q_BUCKET_M    3  /* int64[nb]  edge count of each bucket            */
+#define STTSV_Q_TPTR        4  /* int64[n+1] node-major offsets                   */
+#define STTSV_Q_TSLOT       5  /* int64[nnz] node-major slot lists                */
+#define STTSV_Q_WEIGHTS     6  /* double[r+1] w/|beta| (r-1)! per size (index k)  */
+#define STTSV_Q_SCALE_EXP   7  /* int64[r+1]  FP32 series scale exponent per size */
+                               /*             (INT32_MIN: size runs in FP64)      */
+
+/* Sizes of the plan: m, n, r, nnz, number of buckets, connected flag. */
+typedef struct {
+    int64_t m, nnz;
+    int32_t n, r, nbuckets, connected;
+    int64_t device_bytes;  /* device memory held by the plan                     */
+} sttsv_plan_info;
+
+int sttsv_plan_get_info(sttsv_plan_t plan, sttsv_plan_info* info);
+
+/* Copy one of the arrays above into host memory `out` of `count` elements
+ * (EINVAL if count is not the array's length). */
+int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count);
+
+/* Release a plan and all its device memory.  NULL is a no-op.  Waits for the
+ * plan's stream first. */
+int sttsv_plan_destroy(sttsv_plan_t plan);
+
+/* Static string naming an error code. */
+const char* sttsv_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STTSV_H */

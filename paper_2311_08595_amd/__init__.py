@@ -1,0 +1,119 @@
+"""STTSV on the blowup adjacency tensor of a hypergraph, and H-eigenvector
+centrality by the NQZ iteration, on AMD MI355X (gfx950).
+
+The computation runs in ``libsttsv.so`` (HIP kernels behind a C ABI,
+``include/sttsv.h``); this package only marshals arguments.  PyTorch is used
+for device memory and streams.
+
+    import torch, paper_2311_08595_amd as st
+    plan = st.Plan(eptr, eidx, n, r)                   # host CSR (numpy)
+    y = plan.apply(x)                                  # x: cuda float64 tensor
+    x, info = plan.solve(tol=1e-8)                     # H-eigenvector (Alg. 1)
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import SttsvError, STTSV_MAX_ORDER  # noqa: F401
+
+__all__ = ["Plan", "SttsvError", "load"]
+
+load = _lib.load
+
+
+def _dev_ptr(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous cuda float64 tensor of length %d" % (name, n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Execution plan of one hypergraph (``sttsv_plan``)."""
+
+    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None):
+        import torch
+        lib = _lib.load()
+        self._lib = lib
+        eptr = np.ascontiguousarray(eptr, dtype=np.int64)
+        eidx = np.ascontiguousarray(eidx, dtype=np.int32)
+        self.n, self.r, self.m = int(n), int(r), len(eptr) - 1
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        self.stream = stream
+        opts = _lib.SttsvOpts(_lib.PREC[precision], 0, sptr)
+        h = ctypes.c_void_p()
+        _lib.check(lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, self.m, self.n, self.r,
+                                  ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.precision = precision
+
+    # ------------------------------------------------------------ compute
+    def apply(self, x, y=None, precision=None):
+        """y = B x^(r-1) (TTSV1, Eq. (2)) on the GPU; returns y."""
+        import torch
+        xp = _dev_ptr(x, self.n, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        yp = _dev_ptr(y, self.n, "y")
+        prec = _lib.PREC[precision or self.precision]
+        _lib.check(self._lib.sttsv_apply_prec(self._h, xp, yp, prec))
+        return y
+
+    def solve(self, tol=1e-8, x0=None, out=None, max_iter=500, check_every=8, schedule="fp64",
+              use_graph=True, shift=0.0, switch_tol=1e-6, raise_on_notconv=True):
+        """NQZ iteration (Alg. 1).  Returns (x, info dict); x has l1 norm 1."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        op = _dev_ptr(out, self.n, "out")
+        x0p = None if x0 is None else _dev_ptr(x0, self.n, "x0")
+        o = _lib.SolveOpts(max_iter, check_every, _lib.SCHEDULE[schedule], 1 if use_graph else 0,
+                           float(shift), float(switch_tol))
+        info = _lib.SolveInfo()
+        rc = self._lib.heigvec_solve_ex(self._h, x0p, float(tol), ctypes.byref(o), op, ctypes.byref(info))
+        d = dict(iterations=info.iterations, iters_fp32=info.iters_fp32, iters_fp64=info.iters_fp64,
+                 converged=bool(info.converged), lambda_min=info.lambda_min,
+                 lambda_max=info.lambda_max, criterion=info.criterion, status=rc)
+        if rc != _lib.STTSV_OK and (rc != _lib.STTSV_ENOTCONV or raise_on_notconv):
+            _lib.check(rc)
+        return out, d
+
+    # ------------------------------------------------------- introspection
+    def info(self):
+        pi = _lib.PlanInfo()
+        _lib.check(self._lib.sttsv_plan_get_info(self._h, ctypes.byref(pi)))
+        return dict(m=pi.m, nnz=pi.nnz, n=pi.n, r=pi.r, nbuckets=pi.nbuckets,
+                    connected=bool(pi.connected), device_bytes=pi.device_bytes)
+
+    def query(self, what):
+        inf = self.info()
+        sizes = {_lib.Q_PERM: inf["m"], _lib.Q_MEM: inf["nnz"], _lib.Q_BUCKET_K: inf["nbuckets"],
+                 _lib.Q_BUCKET_M: inf["nbuckets"], _lib.Q_TPTR: inf["n"] + 1,
+                 _lib.Q_TSLOT: inf["nnz"], _lib.Q_WEIGHTS: inf["r"] + 1,
+                 _lib.Q_SCALE_EXP: inf["r"] + 1}
+        cnt = sizes[what]
+        out = np.empty(cnt, dtype=np.float64 if what == _lib.Q_WEIGHTS else np.int64)
+        _lib.check(self._lib.sttsv_plan_query(self._h, what, out.ctypes.data, cnt))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sttsv_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,102 @@
+"""ctypes binding of libsttsv.so (the C ABI in include/sttsv.h).
+
+Argument marshalling only: every step of STTSV and of the solver runs in the
+HIP library.  There is no CPU fallback -- if the library is missing the
+import of any entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsttsv.so")
+
+STTSV_OK = 0
+STTSV_EINVAL = -1
+STTSV_ENOMEM = -2
+STTSV_EDISCONNECTED = -3
+STTSV_ENOTCONV = -4
+STTSV_ENUMERIC = -5
+STTSV_EHIP = -6
+STTSV_ENOTSUP = -7
+STTSV_MAX_ORDER = 64
+
+PREC = {"fp64": 0, "fp32": 1}
+SCHEDULE = {"fp64": 0, "fp32_fp64": 1}
+
+Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP = range(8)
+
+# every symbol the header declares
+EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
+           "heigvec_solve", "heigvec_solve_ex",
+           "sttsv_plan_get_info", "sttsv_plan_query", "sttsv_plan_destroy", "sttsv_strerror"]
+
+
+class SttsvOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("shift", ctypes.c_double), ("switch_tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("iters_fp32", ctypes.c_int32),
+                ("iters_fp64", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("criterion", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("r", ctypes.c_int32), ("nbuckets", ctypes.c_int32), ("connected", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class SttsvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load libsttsv.so (built in-tree by ``paper_2311_08595_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError("libsttsv.so not built: run python -m paper_2311_08595_amd.build "
+                           "(no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.sttsv_plan.argtypes = [P, P, i64, i32, i32, ctypes.POINTER(SttsvOpts), ctypes.POINTER(P)]
+    lib.sttsv_apply.argtypes = [P, P, P]
+    lib.sttsv_apply_prec.argtypes = [P, P, P, i32]
+    lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
+    lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]
+    lib.heigvec_solve_ex.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]
+    lib.sttsv_plan_get_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    lib.sttsv_plan_query.argtypes = [P, i32, P, i64]
+    lib.sttsv_plan_destroy.argtypes = [P]
+    lib.sttsv_strerror.argtypes = [ctypes.c_int]
+    lib.sttsv_strerror.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "sttsv_strerror":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(code):
+    if code != STTSV_OK:
+        raise SttsvError(code, load().sttsv_strerror(code).decode())
+    return code

@@ -1,0 +1,187 @@
+// C ABI entry points (declared in include/sttsv.h).  Every function returns an
+// STTSV_* code; C++ exceptions never cross this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+using sttsv::Plan;
+
+struct sttsv_plan_s {
+  Plan* p;
+};
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return STTSV_ENOMEM;
+  } catch (...) {
+    return STTSV_EINVAL;
+  }
+}
+
+template <typename S, typename D>
+int copy_out(const std::vector<S>& src, void* out, int64_t count) {
+  if ((int64_t)src.size() != count) return STTSV_EINVAL;
+  D* o = static_cast<D*>(out);
+  for (int64_t i = 0; i < count; ++i) o[i] = static_cast<D>(src[i]);
+  return STTSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, int32_t r,
+               const sttsv_opts* opts, sttsv_plan_t* out) {
+  if (out == nullptr) return STTSV_EINVAL;
+  return guarded([&] {
+    Plan* p = nullptr;
+    const int rc = sttsv::build_plan(eptr, eidx, m, n, r, opts, &p);
+    if (rc != STTSV_OK) return rc;
+    *out = new sttsv_plan_s{p};
+    return STTSV_OK;
+  });
+}
+
+int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t precision) {
+  if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr) return STTSV_EINVAL;
+  if (precision != STTSV_PREC_FP64 && precision != STTSV_PREC_FP32) return STTSV_EINVAL;
+  if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
+  return guarded([&] {
+    Plan& p = *plan->p;
+    const hipError_t e = sttsv::launch_sttsv(p, x, y, precision, nullptr, p.stream);
+    return e == hipSuccess ? STTSV_OK : STTSV_EHIP;
+  });
+}
+
+int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t precision, int32_t cap,
+                      int32_t* nstages, int32_t* kinds, int32_t* sizes, int64_t* counts, float* ms) {
+  if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr || nstages == nullptr)
+    return STTSV_EINVAL;
+  if (precision != STTSV_PREC_FP64 && precision != STTSV_PREC_FP32) return STTSV_EINVAL;
+  Plan& p = *plan->p;
+  const int ns = sttsv::stage_count(p);
+  *nstages = ns;
+  if (cap < ns || kinds == nullptr || sizes == nullptr || counts == nullptr || ms == nullptr) return STTSV_EINVAL;
+  return guarded([&] {
+    std::vector<hipEvent_t> ev(ns + 1, nullptr);
+    int rc = STTSV_OK;
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) rc = STTSV_EHIP;
+    if (rc == STTSV_OK && hipEventRecord(ev[0], p.stream) != hipSuccess) rc = STTSV_EHIP;
+    for (int t = 0; t < ns && rc == STTSV_OK; ++t) {
+      if (sttsv::launch_stage(p, t, x, y, precision, nullptr, p.stream) != hipSuccess) rc = STTSV_EHIP;
+      if (rc == STTSV_OK && hipEventRecord(ev[t + 1], p.stream) != hipSuccess) rc = STTSV_EHIP;
+    }
+    if (rc == STTSV_OK && hipEventSynchronize(ev[ns]) != hipSuccess) rc = STTSV_EHIP;
+    for (int t = 0; t < ns && rc == STTSV_OK; ++t) {
+      sttsv::stage_desc(p, t, &kinds[t], &sizes[t], &counts[t]);
+      if (hipEventElapsedTime(&ms[t], ev[t], ev[t + 1]) != hipSuccess) rc = STTSV_EHIP;
+    }
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    return rc;
+  });
+}
+
+int sttsv_apply(sttsv_plan_t plan, const double* x, double* y) {
+  if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
+  return sttsv_apply_prec(plan, x, y, plan->p->precision);
+}
+
+int heigvec_solve_ex(sttsv_plan_t plan, const double* x0, double tol, const sttsv_solve_opts* opts,
+                     double* x_out, sttsv_solve_info* info) {
+  if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
+  sttsv_solve_opts o;
+  o.max_iter = 500;
+  o.check_every = 8;
+  o.schedule = STTSV_SOLVE_FP64;
+  o.use_graph = 1;
+  o.shift = 0.0;
+  o.switch_tol = 1e-6;
+  if (opts != nullptr) o = *opts;
+  return guarded([&] { return sttsv::solve(*plan->p, x0, tol, o, x_out, info); });
+}
+
+int heigvec_solve(sttsv_plan_t plan, const double* x0, double tol, double* x_out, sttsv_solve_info* info) {
+  return heigvec_solve_ex(plan, x0, tol, nullptr, x_out, info);
+}
+
+int sttsv_plan_get_info(sttsv_plan_t plan, sttsv_plan_info* info) {
+  if (plan == nullptr || plan->p == nullptr || info == nullptr) return STTSV_EINVAL;
+  const Plan& p = *plan->p;
+  info->m = p.m;
+  info->nnz = p.nnz;
+  info->n = p.n;
+  info->r = p.r;
+  info->nbuckets = static_cast<int32_t>(p.buckets.size());
+  info->connected = p.connected ? 1 : 0;
+  info->device_bytes = p.device_bytes;
+  return STTSV_OK;
+}
+
+int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) {
+  if (plan == nullptr || plan->p == nullptr || out == nullptr) return STTSV_EINVAL;
+  return guarded([&] {
+    const Plan& p = *plan->p;
+    switch (what) {
+      case STTSV_Q_PERM:
+        return copy_out<int64_t, int64_t>(p.perm, out, count);
+      case STTSV_Q_MEM:
+        return copy_out<int32_t, int64_t>(p.mem, out, count);
+      case STTSV_Q_TPTR:
+        return copy_out<int64_t, int64_t>(p.tptr, out, count);
+      case STTSV_Q_TSLOT:
+        return copy_out<int32_t, int64_t>(p.tslot, out, count);
+      case STTSV_Q_BUCKET_K:
+      case STTSV_Q_BUCKET_M: {
+        std::vector<int64_t> v;
+        for (const auto& b : p.buckets) v.push_back(what == STTSV_Q_BUCKET_K ? b.k : b.m);
+        return copy_out<int64_t, int64_t>(v, out, count);
+      }
+      case STTSV_Q_WEIGHTS:
+        return copy_out<double, double>(p.weights, out, count);
+      case STTSV_Q_SCALE_EXP: {
+        std::vector<int64_t> v(p.r + 1, INT32_MIN);
+        for (const auto& b : p.buckets)
+          if (b.k > 1 && b.fp32_ok) v[b.k] = b.qexp32;
+        return copy_out<int64_t, int64_t>(v, out, count);
+      }
+      default:
+        return STTSV_EINVAL;
+    }
+  });
+}
+
+int sttsv_plan_destroy(sttsv_plan_t plan) {
+  if (plan == nullptr) return STTSV_OK;
+  if (plan->p != nullptr) {
+    (void)hipStreamSynchronize(plan->p->stream);
+    sttsv::free_plan(plan->p);
+  }
+  delete plan;
+  return STTSV_OK;
+}
+
+const char* sttsv_strerror(int code) {
+  switch (code) {
+    case STTSV_OK: return "ok";
+    case STTSV_EINVAL: return "invalid argument or malformed hypergraph";
+    case STTSV_ENOMEM: return "out of memory";
+    case STTSV_EDISCONNECTED: return "hypergraph not connected (H-eigenvector needs a connected hypergraph)";
+    case STTSV_ENOTCONV: return "solver did not converge within max_iter";
+    case STTSV_ENUMERIC: return "non-finite or non-positive value in the solve";
+    case STTSV_EHIP: return "HIP runtime error";
+    case STTSV_ENOTSUP: return "outside the supported range";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

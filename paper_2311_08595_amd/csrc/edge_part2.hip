@@ -1,0 +1,9 @@
+// Instantiates the edge kernels for series windows W = 40..45 (FP64 and FP32).
+#include "edge_kernels.inc"
+
+namespace sttsv {
+void fill_edge_part2(EdgeTables& t) {
+  fill_range<double, 40, 45>(t.f64);
+  fill_range<float, 40, 45>(t.f32);
+}
+}  // namespace sttsv

@@ -1,0 +1,9 @@
+// Instantiates the edge kernels for series windows W = 58..60 (FP64 and FP32).
+#include "edge_kernels.inc"
+
+namespace sttsv {
+void fill_edge_part6(EdgeTables& t) {
+  fill_range<double, 58, 60>(t.f64);
+  fill_range<float, 58, 60>(t.f32);
+}
+}  // namespace sttsv

@@ -1,0 +1,9 @@
+// Instantiates the edge kernels for series windows W = 61..63 (FP64 and FP32).
+#include "edge_kernels.inc"
+
+namespace sttsv {
+void fill_edge_part7(EdgeTables& t) {
+  fill_range<double, 61, 63>(t.f64);
+  fill_range<float, 61, 63>(t.f32);
+}
+}  // namespace sttsv

@@ -1,0 +1,387 @@
+// Host planner: validate the hypergraph, build the canonical layout, the
+// weight table, the reduction schedule, and upload everything to the GPU.
+//
+// Canonical layout (the library's format; the paper's CCSS forest, Sec. III,
+// is its prior art -- edges are sorted vertex sequences, Sec. II-B, grouped by
+// size like the levels L_k of Sec. III):
+//  1. deg(v) = number of edges containing v;
+//  2. vertex order by (deg descending, id ascending); rank(v) = position;
+//  3. every edge lists its members by increasing rank (hubs first);
+//  4. canonical edge order by (size, member-rank sequence, input index);
+//  5. buckets of equal size k, m_k edges each;
+//  6. member slots in structure-of-arrays form: member j of the i-th edge of
+//     bucket k at slot_off(k) + j m_k + i, slot_off(k) = sum_{k'<k} k' m_k';
+//  7. node-major incidence lists: for each v the slots holding v, in
+//     canonical edge order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace sttsv {
+namespace {
+
+struct Dsu {
+  std::vector<int32_t> p;
+  explicit Dsu(int32_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+  int32_t find(int32_t a) {
+    while (p[a] != a) {
+      p[a] = p[p[a]];
+      a = p[a];
+    }
+    return a;
+  }
+  void unite(int32_t a, int32_t b) {
+    a = find(a);
+    b = find(b);
+    if (a != b) p[std::max(a, b)] = std::min(a, b);
+  }
+};
+
+// w(e)/|beta(e)| (r-1)! = (r-1)! / ((k-1)! S(r,k)) for every k <= r
+// (w(e) = |e| and |beta(e)| = |e|! S(r,|e|), Sec. II).  Stirling numbers by
+// their recurrence in extended precision; one rounding to double at the end.
+std::vector<double> weight_table(int r) {
+  std::vector<std::vector<long double>> S(r + 1, std::vector<long double>(r + 1, 0.0L));
+  S[0][0] = 1.0L;
+  for (int a = 1; a <= r; ++a)
+    for (int b = 1; b <= a; ++b) S[a][b] = (long double)b * S[a - 1][b] + S[a - 1][b - 1];
+  std::vector<double> w(r + 1, 0.0);
+  for (int k = 1; k <= r; ++k) {
+    long double num = 1.0L;  // (r-1)!/(k-1)!
+    for (int j = k; j <= r - 1; ++j) num *= (long double)j;
+    w[k] = static_cast<double>(num / S[r][k]);
+  }
+  return w;
+}
+
+double log2_fact(int a) {
+  double s = 0.0;
+  for (int j = 2; j <= a; ++j) s += std::log2((double)j);
+  return s;
+}
+
+// FP32 series range check for edges of size k in an order-r tensor.  With
+// z_i <= rho = 2^q and max z_i > rho/2, every coefficient met is at most
+// max_{d<W} (k rho)^d / d! and the coefficients that matter (g_j, P) are at
+// least (rho/2)^(W-1)/W!.  Pick q to centre that range inside FP32's; report
+// false if it does not fit with margin.
+bool fp32_scale(int r, int k, int* qout) {
+  const int W = r - k + 1;
+  double best = -1e300;
+  int bq = 0;
+  for (int q = -8; q <= 12; ++q) {
+    double hi = 0.0;
+    for (int d = 0; d < W; ++d) hi = std::max(hi, d * (std::log2((double)k) + q) - log2_fact(d));
+    double lo = (W - 1) * (q - 1.0) - log2_fact(W);
+    if (W >= 2) lo = std::min(lo, (W - 2) * (q - 1.0) - log2_fact(W - 1));
+    const double margin = std::min(120.0 - hi, lo + 110.0);
+    if (margin > best) {
+      best = margin;
+      bq = q;
+    }
+  }
+  *qout = bq;
+  return best >= 0.0;
+}
+
+template <typename T>
+int upload(T** dptr, const T* src, size_t count, int64_t* acct) {
+  *dptr = nullptr;
+  if (count == 0) return STTSV_OK;
+  if (hipMalloc(reinterpret_cast<void**>(dptr), count * sizeof(T)) != hipSuccess) {
+    *dptr = nullptr;
+    return STTSV_ENOMEM;
+  }
+  *acct += (int64_t)(count * sizeof(T));
+  if (src != nullptr && hipMemcpy(*dptr, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return STTSV_EHIP;
+  return STTSV_OK;
+}
+
+}  // namespace
+
+void free_plan(Plan* p) {
+  if (p == nullptr) return;
+  free_solver(*p);
+  (void)hipFree(p->d_mem);
+  (void)hipFree(p->d_tslot);
+  (void)hipFree(p->d_contrib);
+  for (auto& L : p->levels) {
+    (void)hipFree(L.d_start);
+    (void)hipFree(L.d_len);
+    (void)hipFree(L.d_dst);
+  }
+  for (double* d : p->d_partials) (void)hipFree(d);
+  for (auto& b : p->buckets) {
+    (void)hipFree(b.gstack64);
+    (void)hipFree(b.gstack32);
+  }
+  delete p;
+}
+
+int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, int32_t r,
+               const sttsv_opts* opts, Plan** out) {
+  if (eptr == nullptr || eidx == nullptr || out == nullptr) return STTSV_EINVAL;
+  if (m < 1 || n < 1) return STTSV_EINVAL;
+  if (r < 2 || r > STTSV_MAX_ORDER) return STTSV_ENOTSUP;
+  if (opts != nullptr && opts->precision != STTSV_PREC_FP64 && opts->precision != STTSV_PREC_FP32)
+    return STTSV_EINVAL;
+  if (eptr[0] != 0) return STTSV_EINVAL;
+  for (int64_t e = 0; e < m; ++e) {
+    const int64_t k = eptr[e + 1] - eptr[e];
+    if (k < 1 || k > r) return STTSV_EINVAL;
+  }
+  const int64_t nnz = eptr[m];
+  if (nnz > INT32_MAX) return STTSV_ENOTSUP;
+
+  // ---- validation of members, degrees
+  std::vector<int64_t> deg(n, 0);
+  {
+    std::vector<int64_t> seen(n, -1);
+    for (int64_t e = 0; e < m; ++e) {
+      for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) {
+        const int32_t v = eidx[p];
+        if (v < 0 || v >= n) return STTSV_EINVAL;
+        if (seen[v] == e) return STTSV_EINVAL;   // repeated vertex in an edge
+        seen[v] = e;
+        deg[v]++;
+      }
+    }
+  }
+
+  Plan* P = new Plan();
+  P->m = m;
+  P->nnz = nnz;
+  P->n = n;
+  P->r = r;
+  P->precision = opts ? opts->precision : STTSV_PREC_FP64;
+  P->stream = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+  (void)hipGetDevice(&P->device);
+
+  // ---- vertex rank: degree descending, id ascending (counting sort by degree)
+  std::vector<int32_t> rank(n);
+  {
+    int64_t maxd = 0;
+    for (int64_t d : deg) maxd = std::max(maxd, d);
+    std::vector<int64_t> cnt(maxd + 2, 0);
+    for (int64_t d : deg) cnt[maxd - d + 1]++;
+    for (int64_t i = 1; i < (int64_t)cnt.size(); ++i) cnt[i] += cnt[i - 1];
+    for (int32_t v = 0; v < n; ++v) rank[v] = static_cast<int32_t>(cnt[maxd - deg[v]]++);
+  }
+
+  // ---- per-edge member ranks, sorted within the edge
+  std::vector<int32_t> rk(nnz);
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t* a = rk.data() + eptr[e];
+    const int64_t k = eptr[e + 1] - eptr[e];
+    for (int64_t j = 0; j < k; ++j) a[j] = rank[eidx[eptr[e] + j]];
+    std::sort(a, a + k);
+  }
+
+  // ---- buckets by size, canonical order inside each
+  std::vector<int64_t> mk(r + 1, 0);
+  for (int64_t e = 0; e < m; ++e) mk[eptr[e + 1] - eptr[e]]++;
+  std::vector<std::vector<int64_t>> members_of(r + 1);
+  for (int k = 1; k <= r; ++k) members_of[k].reserve(mk[k]);
+  for (int64_t e = 0; e < m; ++e) members_of[eptr[e + 1] - eptr[e]].push_back(e);
+
+  std::vector<int32_t> inv_rank(n);
+  for (int32_t v = 0; v < n; ++v) inv_rank[rank[v]] = v;
+
+  P->perm.resize(m);
+  P->mem.resize(nnz);
+  int64_t edge_off = 0, slot_off = 0;
+  for (int k = 1; k <= r; ++k) {
+    auto& ids = members_of[k];
+    if (ids.empty()) continue;
+    struct Key {
+      uint64_t head;
+      int64_t id;
+    };
+    std::vector<Key> keys(ids.size());
+    for (size_t t = 0; t < ids.size(); ++t) {
+      const int32_t* a = rk.data() + eptr[ids[t]];
+      const uint64_t r0 = (uint64_t)(uint32_t)a[0];
+      const uint64_t r1 = k > 1 ? (uint64_t)(uint32_t)a[1] : 0;
+      keys[t] = Key{(r0 << 32) | r1, ids[t]};
+    }
+    std::sort(keys.begin(), keys.end(), [&](const Key& x, const Key& y) {
+      if (x.head != y.head) return x.head < y.head;
+      const int32_t* a = rk.data() + eptr[x.id];
+      const int32_t* b = rk.data() + eptr[y.id];
+      for (int j = 2; j < k; ++j)
+        if (a[j] != b[j]) return a[j] < b[j];
+      return x.id < y.id;
+    });
+    Bucket B;
+    B.k = k;
+    B.m = (int64_t)ids.size();
+    B.edge_off = edge_off;
+    B.slot_off = slot_off;
+    for (int64_t i = 0; i < B.m; ++i) {
+      const int64_t e = keys[i].id;
+      P->perm[edge_off + i] = e;
+      const int32_t* a = rk.data() + eptr[e];
+      for (int j = 0; j < k; ++j) P->mem[slot_off + j * B.m + i] = inv_rank[a[j]];
+    }
+    if (k > 1) B.fp32_ok = fp32_scale(r, k, &B.qexp32);
+    // generic-kernel stack placement: LDS if a 64-thread block needs <= 64 KiB
+    if (k >= 4) {
+      const int W = r - k + 1;
+      const int64_t per64 = 16LL * k + (int64_t)(k - 3) * W * 8;
+      const int64_t per32 = 16LL * k + (int64_t)(k - 3) * W * 4;
+      B.lds64 = per64 * kGenBlock <= 65536 ? 1 : 0;
+      B.lds32 = per32 * kGenBlock <= 65536 ? 1 : 0;
+    }
+    P->buckets.push_back(B);
+    edge_off += B.m;
+    slot_off += (int64_t)k * B.m;
+  }
+  rk.clear();
+  rk.shrink_to_fit();
+
+  // ---- node-major incidence lists in canonical edge order
+  P->tptr.assign(n + 1, 0);
+  for (int32_t v = 0; v < n; ++v) P->tptr[v + 1] = P->tptr[v] + deg[v];
+  P->tslot.resize(nnz);
+  {
+    std::vector<int64_t> cur(P->tptr.begin(), P->tptr.end() - 1);
+    for (const Bucket& B : P->buckets)
+      for (int64_t i = 0; i < B.m; ++i)
+        for (int j = 0; j < B.k; ++j) {
+          const int64_t s = B.slot_off + j * B.m + i;
+          P->tslot[cur[P->mem[s]]++] = static_cast<int32_t>(s);
+        }
+  }
+
+  // ---- connectivity (Perron-Frobenius condition for the solver)
+  {
+    Dsu d(n);
+    for (int64_t e = 0; e < m; ++e)
+      for (int64_t p = eptr[e] + 1; p < eptr[e + 1]; ++p) d.unite(eidx[eptr[e]], eidx[p]);
+    bool ok = true;
+    for (int32_t v = 0; v < n && ok; ++v) ok = deg[v] > 0 && d.find(v) == 0;
+    P->connected = ok;
+  }
+
+  P->weights = weight_table(r);
+
+  // ---- reduction schedule
+  struct HostLevel {
+    std::vector<int32_t> start, len, dst;
+    int64_t in_len = 0;
+  };
+  std::vector<HostLevel> hl;
+  {
+    // level 0 input: contributions gathered through tslot; segment of v = [tptr[v], tptr[v+1])
+    std::vector<int64_t> seg_start(n), seg_len(n);
+    std::vector<int32_t> seg_node(n);
+    for (int32_t v = 0; v < n; ++v) {
+      seg_start[v] = P->tptr[v];
+      seg_len[v] = deg[v];
+      seg_node[v] = v;
+    }
+    int64_t in_len = nnz;
+    bool first = true;
+    while (!seg_node.empty()) {
+      HostLevel L;
+      L.in_len = in_len;
+      std::vector<int64_t> nstart, nlen;
+      std::vector<int32_t> nnode;
+      int64_t next_len = 0;
+      for (size_t q = 0; q < seg_node.size(); ++q) {
+        const int64_t d = seg_len[q];
+        const int64_t nch = d <= kChunk ? 1 : (d + kChunk - 1) / kChunk;
+        if (nch == 1) {
+          L.start.push_back(static_cast<int32_t>(d > 0 ? seg_start[q] : 0));
+          L.len.push_back(static_cast<int32_t>(d));
+          L.dst.push_back(seg_node[q]);
+        } else {
+          for (int64_t c = 0; c < nch; ++c) {
+            L.start.push_back(static_cast<int32_t>(seg_start[q] + c * kChunk));
+            L.len.push_back(static_cast<int32_t>(std::min<int64_t>(kChunk, d - c * kChunk)));
+            L.dst.push_back(static_cast<int32_t>(-(next_len + c) - 1));
+          }
+          nstart.push_back(next_len);
+          nlen.push_back(nch);
+          nnode.push_back(seg_node[q]);
+          next_len += nch;
+        }
+      }
+      if (first) {
+        // longest chunks first so that the lanes of a wave do similar work
+        std::vector<int64_t> o(L.len.size());
+        std::iota(o.begin(), o.end(), 0);
+        std::stable_sort(o.begin(), o.end(), [&](int64_t a, int64_t b) { return L.len[a] > L.len[b]; });
+        HostLevel S;
+        S.in_len = L.in_len;
+        S.start.resize(o.size());
+        S.len.resize(o.size());
+        S.dst.resize(o.size());
+        for (size_t t = 0; t < o.size(); ++t) {
+          S.start[t] = L.start[o[t]];
+          S.len[t] = L.len[o[t]];
+          S.dst[t] = L.dst[o[t]];
+        }
+        L = std::move(S);
+        first = false;
+      }
+      hl.push_back(std::move(L));
+      seg_start = std::move(nstart);
+      seg_len = std::move(nlen);
+      seg_node = std::move(nnode);
+      in_len = next_len;
+    }
+  }
+
+  // ---- device uploads
+  int rc = STTSV_OK;
+  auto fail = [&](int code) {
+    free_plan(P);
+    return code;
+  };
+  if ((rc = upload(&P->d_mem, P->mem.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload(&P->d_tslot, P->tslot.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  for (size_t l = 0; l < hl.size(); ++l) {
+    ReduceLevel L;
+    L.nchunks = (int64_t)hl[l].len.size();
+    L.in_len = hl[l].in_len;
+    P->levels.push_back(L);
+    ReduceLevel& D = P->levels.back();
+    if ((rc = upload(&D.d_start, hl[l].start.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    if ((rc = upload(&D.d_len, hl[l].len.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    if ((rc = upload(&D.d_dst, hl[l].dst.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    if (l + 1 < hl.size()) {
+      double* part = nullptr;
+      if ((rc = upload<double>(&part, nullptr, hl[l + 1].in_len, &P->device_bytes)) != STTSV_OK) return fail(rc);
+      P->d_partials.push_back(part);
+    }
+  }
+  for (Bucket& B : P->buckets) {
+    if (B.k < 4) continue;
+    const int W = r - B.k + 1;
+    const size_t scal = 2 * (size_t)B.k * B.m * sizeof(double);
+    if (!B.lds64) {
+      const size_t bytes = scal + (size_t)(B.k - 3) * W * B.m * sizeof(double);
+      if (hipMalloc(&B.gstack64, bytes) != hipSuccess) return fail(STTSV_ENOMEM);
+      P->device_bytes += (int64_t)bytes;
+    }
+    if (!B.lds32 && B.fp32_ok) {
+      const size_t bytes = scal + (size_t)(B.k - 3) * W * B.m * sizeof(float);
+      if (hipMalloc(&B.gstack32, bytes) != hipSuccess) return fail(STTSV_ENOMEM);
+      P->device_bytes += (int64_t)bytes;
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(STTSV_EHIP);
+  *out = P;
+  return STTSV_OK;
+}
+
+}  // namespace sttsv

@@ -1,0 +1,68 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects malformed input before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2311_08595_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sttsv.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH), reason="libsttsv.so not built")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_lists_every_export():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.sttsv_strerror(0) == b"ok"
+    assert b"connected" in lib.sttsv_strerror(_lib.STTSV_EDISCONNECTED)
+
+
+def _plan(eptr, eidx, m, n, r):
+    lib = _lib.load()
+    eptr = np.ascontiguousarray(eptr, dtype=np.int64)
+    eidx = np.ascontiguousarray(eidx, dtype=np.int32)
+    h = ctypes.c_void_p()
+    rc = lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, m, n, r, None, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case,code", [
+    (([0, 2], [0, 0], 1, 3, 3), _lib.STTSV_EINVAL),          # repeated vertex in an edge
+    (([0, 4], [0, 1, 2, 3], 1, 4, 3), _lib.STTSV_EINVAL),    # |e| > r
+    (([0, 2], [0, 7], 1, 4, 3), _lib.STTSV_EINVAL),          # vertex id out of range
+    (([0, 2], [0, -1], 1, 4, 3), _lib.STTSV_EINVAL),         # negative id
+    (([0, 0, 2], [0, 1], 2, 4, 3), _lib.STTSV_EINVAL),       # empty edge
+    (([1, 3], [0, 1, 2], 1, 4, 3), _lib.STTSV_EINVAL),       # eptr[0] != 0
+    (([0, 2], [0, 1], 1, 4, 1), _lib.STTSV_ENOTSUP),         # r < 2
+    (([0, 2], [0, 1], 1, 4, 65), _lib.STTSV_ENOTSUP),        # r above the maximum
+    (([0, 2], [0, 1], 0, 4, 3), _lib.STTSV_EINVAL),          # m = 0
+    (([0, 2], [0, 1], 1, 0, 3), _lib.STTSV_EINVAL),          # n = 0
+])
+def test_plan_rejects_malformed_input(case, code):
+    rc, h = _plan(*case)
+    assert rc == code and not h.value
+
+
+def test_null_arguments():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.sttsv_plan(None, None, 1, 1, 2, None, ctypes.byref(h)) == _lib.STTSV_EINVAL
+    assert lib.sttsv_apply(None, None, None) == _lib.STTSV_EINVAL
+    assert lib.heigvec_solve(None, None, 1e-8, None, None) == _lib.STTSV_EINVAL
+    assert lib.sttsv_plan_destroy(None) == _lib.STTSV_OK

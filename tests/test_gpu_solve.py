@@ -112,5 +112,8 @@ def test_solver_errors():
         with pytest.raises(SttsvError) as e:
             plan.solve(x0=bad)
         assert e.value.code == _lib.STTSV_EINVAL
+    eptr, eidx = _csr([(0, 1, 2), (1, 2, 3), (0, 3), (3, 4), (4, 5, 1), (2, 5)])
+    with st.Plan(eptr, eidx, 6, 4) as plan:
         x, info = plan.solve(tol=1e-300, max_iter=3, raise_on_notconv=False)
         assert info["status"] == _lib.STTSV_ENOTCONV and info["iterations"] == 3
+        assert info["criterion"] > 0

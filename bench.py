@@ -70,24 +70,47 @@ def stage_table(plan, xd, yd, prec, reps):
             for i in range(ns.value)]
 
 
-def roofline_of(stages, r, prec):
+GEN_LO = [1, 9, 17, 25, 33, 41, 49, 57]
+GEN_HI = [8, 16, 24, 32, 40, 48, 56, 63]
+
+
+def stage_work(stages, bucket_k, bucket_m, r):
+    """Algorithmic FLOPs and HBM bytes of every stage.  Edge stages: series
+    FMAs x 2 and 20 B per incidence; fused generic stages: the same summed over
+    the buckets that no per-bucket stage covers and whose window is in the
+    stage's range; reduction levels: 8 B per term read, 12 B per chunk
+    descriptor, 8 B per result written."""
+    per_bucket = {s["size"] for s in stages if s["kind"] == 0}
+    out = []
+    for s in stages:
+        if s["kind"] == 0:
+            k, m = s["size"], s["count"]
+            out.append((2.0 * edge_fma(k, r) * m, edge_bytes(k) * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m)))
+        elif s["kind"] == 1:
+            g = s["size"]
+            f = b = 0.0
+            for k, m in zip(bucket_k, bucket_m):
+                W = r - k + 1
+                if k >= 4 and k not in per_bucket and GEN_LO[g] <= W <= GEN_HI[g]:
+                    f += 2.0 * edge_fma(k, r) * m
+                    b += edge_bytes(k) * m
+            out.append((f, b, "generic edges W in [%d,%d], %d edges" % (GEN_LO[g], GEN_HI[g], s["count"])))
+        else:
+            out.append((0.0, 8.0 * s["in_len"] + 20.0 * s["count"], "reduce level %d, %d chunks" % (s["size"], s["count"])))
+    return out
+
+
+def roofline_of(stages, work, prec):
     """Dominant stage and its roofline figures."""
-    best = max(stages, key=lambda s: s["ms"])
-    t = best["ms"] * 1e-3
-    if best["kind"] == 0:
-        k, m = best["size"], best["count"]
-        flops = 2.0 * edge_fma(k, r) * m
-        byts = edge_bytes(k) * m
-        peak_f = PEAK_FP64_VALU if prec == "fp64" else PEAK_FP64_VALU  # non-packed FP32 = FP64 rate
-        if flops / peak_f >= byts / PEAK_HBM:
-            return best, dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
-                              frac=(flops / t) / peak_f, traffic=None,
-                              kernel="edge k=%d (W=%d), %d edges" % (k, r - k + 1, m))
-        return best, dict(bound="hbm", achieved=byts / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                          frac=(byts / t) / PEAK_HBM, traffic=None,
-                          kernel="edge k=%d (W=%d), %d edges" % (k, r - k + 1, m))
-    return best, dict(bound="hbm", achieved=None, peak=PEAK_HBM / 1e9, unit="GB/s", frac=None,
-                      traffic=None, kernel="reduce level %d" % best["size"])
+    i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
+    t = stages[i]["ms"] * 1e-3
+    flops, byts, name = work[i]
+    peak_f = PEAK_FP64_VALU      # FP64 FMA and non-packed FP32 FMA issue at the same rate
+    if flops / peak_f >= byts / PEAK_HBM:
+        return stages[i], dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
+                               frac=(flops / t) / peak_f, traffic=None, kernel=name)
+    return stages[i], dict(bound="hbm", achieved=byts / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                           frac=(byts / t) / PEAK_HBM, traffic=None, kernel=name)
 
 
 def cpu_baseline(w, sample_edges, seed=0):
@@ -140,7 +163,8 @@ def main():
     xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
     yd = torch.empty_like(xd)
 
-    res = {}
+    from paper_2311_08595_amd import _lib as L
+    res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist()}
     for prec in ("fp64", "fp32"):
         log("[bench] timing STTSV %s" % prec)
         for _ in range(a.warmup):
@@ -152,6 +176,13 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
         stages = stage_table(plan, xd, yd, prec, a.stage_reps)
+        # terms read by each reduction level: nnz at level 0, at most the previous
+        # level's chunk count above it
+        prev = len(w["eidx"])
+        for st_ in stages:
+            if st_["kind"] == 2:
+                st_["in_len"] = prev
+                prev = st_["count"]
         res[prec] = dict(ms=dt * 1e3, stages=stages)
         log("[bench]   %s: %.3f ms/STTSV, %.3e hyperedges/s" % (prec, dt * 1e3, m / dt))
 
@@ -172,10 +203,14 @@ def main():
                    "sizes": "P(k)~k^-2.5 on [2,25]", "membership": "Zipf(1.0)",
                    "parallelism": "1 GPU"},
     }
-    best, roof = roofline_of(res["fp64"]["stages"], r, "fp64")
+    from paper_2311_08595_amd import _lib
+    bk, bm = res["bucket_k"], res["bucket_m"]
+    for prec in ("fp64", "fp32"):
+        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r)
+    best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64")
     roof["avg_kernel_ms"] = best["ms"]
     out["roofline"] = roof
-    best32, roof32 = roofline_of(res["fp32"]["stages"], r, "fp32")
+    best32, roof32 = roofline_of(res["fp32"]["stages"], res["fp32"]["work"], "fp32")
     roof32["avg_kernel_ms"] = best32["ms"]
     out["fp32_series"] = {"value": m / (res["fp32"]["ms"] * 1e-3), "ms_per_step": res["fp32"]["ms"],
                           "roofline": roof32}

@@ -53,10 +53,15 @@ extern "C" {
 
 typedef struct sttsv_plan_s* sttsv_plan_t;
 
+/* Plan flags. */
+#define STTSV_FLAG_GENERIC_ONLY 1  /* run every edge of size >= 4 through the generic */
+                                   /* (runtime-size) kernel instead of the register-  */
+                                   /* resident ones; results are bitwise identical    */
+
 /* Options for sttsv_plan.  Pass NULL for all defaults. */
 typedef struct {
     int32_t precision;   /* STTSV_PREC_FP64 (default) or STTSV_PREC_FP32        */
-    int32_t reserved0;
+    int32_t flags;       /* STTSV_FLAG_* bits (default 0)                        */
     void*   stream;      /* hipStream_t the plan's work is ordered on; NULL =   */
                          /* the default stream                                   */
 } sttsv_opts;
@@ -106,10 +111,12 @@ int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t prec
  * sttsv_apply_timed -- sttsv_apply_prec, with every stage timed by a pair of
  * hipEvents recorded on the plan's stream (for measurement tools).
  *
- * Stage s is either the edge-kernel launch of one size bucket
- * (kinds[s] = 0, sizes[s] = edge size k, counts[s] = edges in the bucket) or
- * one level of the node reduction (kinds[s] = 1, sizes[s] = level,
- * counts[s] = chunks).  ms[s] = elapsed milliseconds of that stage.
+ * Stage s is one of: the edge-kernel launch of one size bucket
+ * (kinds[s] = 0, sizes[s] = edge size k, counts[s] = edges in the bucket);
+ * a fused launch of the generic kernel over several buckets (kinds[s] = 1,
+ * sizes[s] = window-range index, counts[s] = edges covered); one level of
+ * the node reduction (kinds[s] = 2, sizes[s] = level, counts[s] = chunks).
+ * ms[s] = elapsed milliseconds of that stage.
  *   cap      capacity of the four host output arrays (entries)
  *   nstages  host: number of stages (set even when cap is too small, then
  *            EINVAL is returned and nothing is launched)

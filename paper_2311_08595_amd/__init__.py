@@ -34,7 +34,7 @@ def _dev_ptr(t, n, name):
 class Plan:
     """Execution plan of one hypergraph (``sttsv_plan``)."""
 
-    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None):
+    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None, flags=0):
         import torch
         lib = _lib.load()
         self._lib = lib
@@ -45,7 +45,7 @@ class Plan:
             stream = torch.cuda.current_stream()
         sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
         self.stream = stream
-        opts = _lib.SttsvOpts(_lib.PREC[precision], 0, sptr)
+        opts = _lib.SttsvOpts(_lib.PREC[precision], int(flags), sptr)
         h = ctypes.c_void_p()
         _lib.check(lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, self.m, self.n, self.r,
                                   ctypes.byref(opts), ctypes.byref(h)))

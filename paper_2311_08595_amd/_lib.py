@@ -21,6 +21,7 @@ STTSV_ENUMERIC = -5
 STTSV_EHIP = -6
 STTSV_ENOTSUP = -7
 STTSV_MAX_ORDER = 64
+FLAG_GENERIC_ONLY = 1
 
 PREC = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"fp64": 0, "fp32_fp64": 1}
@@ -34,7 +35,7 @@ EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
 
 
 class SttsvOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 

@@ -20,9 +20,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsttsv.so")
 ARCH = os.environ.get("STTSV_ARCH", "gfx950")
 
-HIP_SOURCES = ["edge_part%d.hip" % i for i in range(8)] + ["apply.hip", "reduce.hip", "nqz.hip"]
+HIP_SOURCES = (["edge_part%d.hip" % i for i in range(8)] + ["edge_gen%d.hip" % i for i in range(8)]
+               + ["apply.hip", "reduce.hip", "nqz.hip"])
 CXX_SOURCES = ["plan.cpp", "api.cpp"]
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off"]
 
 
 def _hipcc():

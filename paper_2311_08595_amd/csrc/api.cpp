@@ -67,7 +67,7 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
     return STTSV_EINVAL;
   if (precision != STTSV_PREC_FP64 && precision != STTSV_PREC_FP32) return STTSV_EINVAL;
   Plan& p = *plan->p;
-  const int ns = sttsv::stage_count(p);
+  const int ns = sttsv::stage_count(p, precision);
   *nstages = ns;
   if (cap < ns || kinds == nullptr || sizes == nullptr || counts == nullptr || ms == nullptr) return STTSV_EINVAL;
   return guarded([&] {
@@ -82,7 +82,7 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
     }
     if (rc == STTSV_OK && hipEventSynchronize(ev[ns]) != hipSuccess) rc = STTSV_EHIP;
     for (int t = 0; t < ns && rc == STTSV_OK; ++t) {
-      sttsv::stage_desc(p, t, &kinds[t], &sizes[t], &counts[t]);
+      sttsv::stage_desc(p, precision, t, &kinds[t], &sizes[t], &counts[t]);
       if (hipEventElapsedTime(&ms[t], ev[t], ev[t + 1]) != hipSuccess) rc = STTSV_EHIP;
     }
     for (auto& e : ev)

@@ -1,5 +1,6 @@
-// STTSV launch sequence: one edge-major launch per size bucket (kernel picked
-// by edge size and series window), then the deterministic node reduction.
+// STTSV launch sequence: per-bucket edge kernels (k = 1, 2, 3 and the
+// register-resident k <= 7 kernels), one fused launch per window range for the
+// generic buckets, then the deterministic node reduction.
 #include "internal.hpp"
 
 namespace sttsv {
@@ -12,25 +13,33 @@ void fill_edge_part4(EdgeTables&);
 void fill_edge_part5(EdgeTables&);
 void fill_edge_part6(EdgeTables&);
 void fill_edge_part7(EdgeTables&);
+void fill_edge_gen0(EdgeTables&);
+void fill_edge_gen1(EdgeTables&);
+void fill_edge_gen2(EdgeTables&);
+void fill_edge_gen3(EdgeTables&);
+void fill_edge_gen4(EdgeTables&);
+void fill_edge_gen5(EdgeTables&);
+void fill_edge_gen6(EdgeTables&);
+void fill_edge_gen7(EdgeTables&);
 
 namespace {
 
 // Size-1 edges {v}: beta = {(v,..,v)}, value 1, so the term is x_v^(r-1).
-__global__ void __launch_bounds__(256) edge_k1(EdgeLaunch a) {
-  if (a.done != nullptr && *a.done) return;
+__global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
+  if (c.done != nullptr && *c.done) return;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.m) return;
-  const double xv = a.x[a.mem[i]];
+  if (i >= b.m) return;
+  const double xv = c.x[b.mem[i]];
   int e2 = 0;
   const double f = frexp(xv, &e2);          // xv = f 2^e2
   double p = 1.0;
-  for (int j = 0; j < a.r - 1; ++j) p *= f;
-  a.contrib[i] = ldexp(p, (a.r - 1) * e2);
+  for (int j = 0; j < b.r - 1; ++j) p *= f;
+  c.contrib[b.pos[i]] = ldexp(p, (b.r - 1) * e2);
 }
 
-hipError_t launch_k1(const EdgeLaunch& a, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>((a.m + 255) / 256));
-  hipLaunchKernelGGL(edge_k1, grid, dim3(256), 0, s, a);
+hipError_t launch_k1(const EdgeCall& c, const BucketDesc& b, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((b.m + 255) / 256));
+  hipLaunchKernelGGL(edge_k1, grid, dim3(256), 0, s, c, b);
   return hipGetLastError();
 }
 
@@ -44,10 +53,15 @@ EdgeTables build_tables() {
   fill_edge_part5(t);
   fill_edge_part6(t);
   fill_edge_part7(t);
-  for (int w = 0; w <= kMaxW; ++w) {
-    t.f64[KIND_K1][w] = &launch_k1;
-    t.f32[KIND_K1][w] = &launch_k1;
-  }
+  fill_edge_gen0(t);
+  fill_edge_gen1(t);
+  fill_edge_gen2(t);
+  fill_edge_gen3(t);
+  fill_edge_gen4(t);
+  fill_edge_gen5(t);
+  fill_edge_gen6(t);
+  fill_edge_gen7(t);
+  t.k1 = &launch_k1;
   return t;
 }
 
@@ -58,45 +72,51 @@ const EdgeTables& edge_tables() {
   return t;
 }
 
-static int kind_of(int k) { return k == 1 ? KIND_K1 : k == 2 ? KIND_K2 : k == 3 ? KIND_K3 : KIND_KG; }
+void build_stages(Plan& p) {
+  for (int seq = 0; seq < 2; ++seq) {
+    std::vector<Stage>& st = p.stages[seq];
+    st.clear();
+    for (size_t b = 0; b < p.buckets.size(); ++b) {
+      const Bucket& B = p.buckets[b];
+      const bool f64 = seq == 0 || !B.fp32_ok || B.k == 1;
+      if (B.k == 1 || B.small_kind[f64 ? 0 : 1] >= 0) st.push_back(Stage{0, static_cast<int>(b), f64});
+    }
+    for (size_t g = 0; g < p.groups.size(); ++g)
+      if (p.groups[g].seq == seq) st.push_back(Stage{1, static_cast<int>(g), p.groups[g].f64});
+    for (size_t l = 0; l < p.levels.size(); ++l) st.push_back(Stage{2, static_cast<int>(l), true});
+  }
+}
 
-int stage_count(const Plan& p) { return static_cast<int>(p.buckets.size() + p.levels.size()); }
+int stage_count(const Plan& p, int precision) {
+  return static_cast<int>(p.stages[precision == STTSV_PREC_FP32 ? 1 : 0].size());
+}
 
 hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s) {
-  const int nb = static_cast<int>(p.buckets.size());
-  if (stage < nb) {
-    const EdgeTables& tab = edge_tables();
-    const Bucket& b = p.buckets[stage];
-    const bool f32 = precision == STTSV_PREC_FP32 && b.fp32_ok && b.k > 1;
-    EdgeLaunch a;
-    a.x = x;
-    a.mem = p.d_mem + b.slot_off;
-    a.contrib = p.d_contrib + b.slot_off;
-    a.done = done;
-    a.m = b.m;
-    a.k = b.k;
-    a.r = p.r;
-    a.qexp = f32 ? b.qexp32 : 0;
-    a.lds_stack = f32 ? b.lds32 : b.lds64;
-    a.gstack = f32 ? b.gstack32 : b.gstack64;
-    a.wk = p.weights[b.k];
-    const int W = p.r - b.k + 1;
-    const int kind = kind_of(b.k);
-    const int wi = kind == KIND_K1 ? 0 : W;
-    EdgeLaunchFn fn = f32 ? tab.f32[kind][wi] : tab.f64[kind][wi];
-    if (fn == nullptr) return hipErrorInvalidValue;
-    return fn(a, s);
+  const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
+  const EdgeTables& tab = edge_tables();
+  const EdgeCall c{x, p.d_contrib, done};
+  if (S.type == 0) {
+    const Bucket& B = p.buckets[S.index];
+    const BucketDesc& d = B.desc[S.f64 ? 0 : 1];
+    if (B.k == 1) return tab.k1(c, d, s);
+    const SmallLaunchFn fn = S.f64 ? tab.small64[B.small_kind[0]][d.W] : tab.small32[B.small_kind[1]][d.W];
+    return fn ? fn(c, d, s) : hipErrorInvalidValue;
   }
-  const size_t l = static_cast<size_t>(stage - nb);
+  if (S.type == 1) {
+    const GenGroup& G = p.groups[S.index];
+    const GenLaunchFn fn = G.f64 ? tab.gen64[G.range] : tab.gen32[G.range];
+    return fn ? fn(c, G.d_bks, G.d_tasks, G.ntasks, G.lds, s) : hipErrorInvalidValue;
+  }
+  const size_t l = static_cast<size_t>(S.index);
   const double* in = l == 0 ? p.d_contrib : p.d_partials[l - 1];
   double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
-  return launch_reduce_level(p.levels[l], static_cast<int>(l), in, p.d_tslot, y, next, done, s);
+  return launch_reduce_level(p.levels[l], in, y, next, done, s);
 }
 
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s) {
-  const int ns = stage_count(p);
+  const int ns = stage_count(p, precision);
   for (int t = 0; t < ns; ++t) {
     const hipError_t e = launch_stage(p, t, x, y, precision, done, s);
     if (e != hipSuccess) return e;
@@ -104,16 +124,20 @@ hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
   return hipSuccess;
 }
 
-void stage_desc(const Plan& p, int stage, int32_t* kind, int32_t* size, int64_t* count) {
-  const int nb = static_cast<int>(p.buckets.size());
-  if (stage < nb) {
-    *kind = 0;
-    *size = p.buckets[stage].k;
-    *count = p.buckets[stage].m;
+void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t* size, int64_t* count) {
+  const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
+  *kind = S.type;
+  if (S.type == 0) {
+    *size = p.buckets[S.index].k;
+    *count = p.buckets[S.index].m;
+  } else if (S.type == 1) {
+    *size = p.groups[S.index].range;
+    int64_t m = 0;
+    for (int b : p.groups[S.index].buckets) m += p.buckets[b].m;
+    *count = m;
   } else {
-    *kind = 1;
-    *size = stage - nb;
-    *count = p.levels[stage - nb].nchunks;
+    *size = S.index;
+    *count = p.levels[S.index].nchunks;
   }
 }
 

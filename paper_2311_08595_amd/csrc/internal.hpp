@@ -11,36 +11,66 @@
 
 namespace sttsv {
 
-// Kinds of edge kernels (by edge size k).
-enum EdgeKind : int { KIND_K1 = 0, KIND_K2 = 1, KIND_K3 = 2, KIND_KG = 3, KIND_COUNT = 4 };
+// Edge kernels by edge size k: k = 1, 2, 3 have their own kernels; for
+// 4 <= k <= 7 a register-resident kernel with k fixed at compile time is used
+// where its series fit in registers; every other k >= 4 runs the generic
+// kernel (runtime k, suffix stack in LDS or global memory), whose buckets are
+// fused into one launch per window range.  All variants perform the same
+// operations in the same order, so their contributions are bitwise identical.
+enum SmallKind : int { SK_K2 = 0, SK_K3 = 1, SK_R4 = 2, SK_R5 = 3, SK_R6 = 4, SK_R7 = 5, SK_COUNT = 6 };
 
 constexpr int kMaxW = STTSV_MAX_ORDER;   // windows W = r - k + 1 <= r - 1 for k >= 2
 constexpr int kGenBlock = 64;            // threads per block of the generic kernel
-constexpr int kSmallBlock = 256;         // threads per block of the k <= 3 kernels
+constexpr int kSmallBlock = 256;         // threads per block of the other edge kernels
 constexpr int kChunk = 32;               // reduction chunk length (fixed: part of the format)
+constexpr int kGenRanges = 8;            // window ranges of the fused generic kernels
+constexpr int kGenLo[kGenRanges] = {1, 9, 17, 25, 33, 41, 49, 57};
+constexpr int kGenHi[kGenRanges] = {8, 16, 24, 32, 40, 48, 56, 63};
+constexpr int64_t kLdsBudget = 40 * 1024;  // LDS per generic block (>= 4 blocks per CU)
 
-// Arguments of one bucket launch (all device pointers already offset to the
-// bucket's slot range).
-struct EdgeLaunch {
+inline int gen_range_of(int W) {
+  for (int g = 0; g < kGenRanges; ++g)
+    if (W >= kGenLo[g] && W <= kGenHi[g]) return g;
+  return -1;
+}
+
+// Per-call arguments of the edge kernels.
+struct EdgeCall {
   const double* x;      // input vector
-  const int32_t* mem;   // member slots of the bucket, SoA: mem[j*m + i]
-  double* contrib;      // contributions, same slot layout as mem
-  void* gstack;         // global suffix stack for the generic kernel (or null)
+  double* contrib;      // per-incidence contributions, node-major order
   const int32_t* done;  // early-exit flag (solver), nullable
+};
+
+// Plan-time description of one size bucket (device pointers offset to the
+// bucket's slot range).
+struct BucketDesc {
+  const int32_t* mem;   // member ids, SoA: mem[j*m + i]
+  const int32_t* pos;   // node-major position of each member slot, same layout
+  void* gstack;         // generic kernel: per-edge global stack (when not in LDS)
   int64_t m;            // edges in the bucket
-  int32_t k;            // edge size
-  int32_t r;            // tensor order
+  int32_t k, r, W;      // edge size, tensor order, series window r - k + 1
   int32_t qexp;         // series scale exponent (rho = 2^qexp)
-  int32_t lds_stack;    // 1: suffix stack in LDS, 0: in gstack
+  int32_t lds_stack;    // generic kernel: 1 = stack in LDS
+  int32_t pad;
   double wk;            // w(e)/|beta(e)| (r-1)!
 };
 
-using EdgeLaunchFn = hipError_t (*)(const EdgeLaunch&, hipStream_t);
+// One block of a fused generic launch: 64 consecutive edges of a bucket.
+struct GenTask {
+  int32_t bucket;
+  int32_t block;
+};
 
-// Function tables indexed [kind][W], filled by the instantiation units.
+using SmallLaunchFn = hipError_t (*)(const EdgeCall&, const BucketDesc&, hipStream_t);
+using GenLaunchFn = hipError_t (*)(const EdgeCall&, const BucketDesc* bks, const GenTask* tasks,
+                                   int64_t ntasks, size_t lds, hipStream_t);
+
 struct EdgeTables {
-  EdgeLaunchFn f64[KIND_COUNT][kMaxW + 1];
-  EdgeLaunchFn f32[KIND_COUNT][kMaxW + 1];
+  SmallLaunchFn small64[SK_COUNT][kMaxW + 1];
+  SmallLaunchFn small32[SK_COUNT][kMaxW + 1];
+  GenLaunchFn gen64[kGenRanges];
+  GenLaunchFn gen32[kGenRanges];
+  SmallLaunchFn k1;
 };
 const EdgeTables& edge_tables();
 
@@ -60,15 +90,36 @@ struct Bucket {
   int64_t slot_off = 0;   // first member slot
   int32_t qexp32 = 0;     // FP32 series scale exponent
   bool fp32_ok = true;    // FP32 series representable for this size
-  int32_t lds64 = 1, lds32 = 1;  // stack placement per precision (generic kind)
-  void* gstack64 = nullptr;
-  void* gstack32 = nullptr;
+  void* gstack[2] = {nullptr, nullptr};  // generic-kernel global stacks [fp64, fp32]
+  BucketDesc desc[2];     // [fp64 series, fp32 series]
+  int small_kind[2] = {-1, -1};          // SmallKind, or -1: generic / k = 1
+};
+
+// A fused generic launch: all generic buckets of one precision whose window
+// falls in one range.
+struct GenGroup {
+  int range = 0;
+  int seq = 0;          // launch sequence: 0 = FP64 apply, 1 = FP32-series apply
+  bool f64 = true;      // series type of the group's kernels
+  int64_t ntasks = 0;
+  size_t lds = 0;
+  BucketDesc* d_bks = nullptr;
+  GenTask* d_tasks = nullptr;
+  std::vector<int> buckets;
+};
+
+// One launch of the STTSV sequence.
+struct Stage {
+  int type;      // 0 = per-bucket edge kernel, 1 = fused generic group, 2 = reduction level
+  int index;     // bucket, group or level
+  bool f64;      // series type of an edge stage
 };
 
 struct Plan {
   int64_t m = 0, nnz = 0;
   int32_t n = 0, r = 0;
   int32_t precision = STTSV_PREC_FP64;
+  int32_t flags = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   bool connected = false;
@@ -85,8 +136,10 @@ struct Plan {
 
   // device buffers
   int32_t* d_mem = nullptr;
-  int32_t* d_tslot = nullptr;
-  double* d_contrib = nullptr;
+  int32_t* d_pos = nullptr;       // node-major position of every member slot
+  double* d_contrib = nullptr;    // node-major contributions
+  std::vector<GenGroup> groups;   // fused generic launches (both precisions)
+  std::vector<Stage> stages[2];   // launch sequence per precision [fp64, fp32]
   std::vector<ReduceLevel> levels;
   std::vector<double*> d_partials;   // partial arrays for levels >= 1
 
@@ -99,18 +152,18 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
                const sttsv_opts* opts, Plan** out);
 void free_plan(Plan* p);
 
-// STTSV launch sequence (apply.hip): one stage per size bucket (edge
-// kernel), then one stage per reduction level.
+// STTSV launch sequence (apply.hip): per-bucket edge kernels and fused
+// generic groups, then one stage per reduction level.
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s);
-int stage_count(const Plan& p);
+int stage_count(const Plan& p, int precision);
 hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s);
-void stage_desc(const Plan& p, int stage, int32_t* kind, int32_t* size, int64_t* count);
+void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t* size, int64_t* count);
+void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
 
 // reduction kernels (reduce.hip)
-hipError_t launch_reduce_level(const ReduceLevel& L, int level, const double* in,
-                               const int32_t* tslot, double* y, double* next,
+hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
                                const int32_t* done, hipStream_t s);
 
 // solver (nqz.hip)

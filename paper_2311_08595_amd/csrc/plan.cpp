@@ -110,8 +110,12 @@ void free_plan(Plan* p) {
   if (p == nullptr) return;
   free_solver(*p);
   (void)hipFree(p->d_mem);
-  (void)hipFree(p->d_tslot);
+  (void)hipFree(p->d_pos);
   (void)hipFree(p->d_contrib);
+  for (auto& g : p->groups) {
+    (void)hipFree(g.d_bks);
+    (void)hipFree(g.d_tasks);
+  }
   for (auto& L : p->levels) {
     (void)hipFree(L.d_start);
     (void)hipFree(L.d_len);
@@ -119,8 +123,8 @@ void free_plan(Plan* p) {
   }
   for (double* d : p->d_partials) (void)hipFree(d);
   for (auto& b : p->buckets) {
-    (void)hipFree(b.gstack64);
-    (void)hipFree(b.gstack32);
+    (void)hipFree(b.gstack[0]);
+    (void)hipFree(b.gstack[1]);
   }
   delete p;
 }
@@ -161,6 +165,7 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
   P->n = n;
   P->r = r;
   P->precision = opts ? opts->precision : STTSV_PREC_FP64;
+  P->flags = opts ? opts->flags : 0;
   P->stream = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
   (void)hipGetDevice(&P->device);
 
@@ -231,14 +236,6 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
       for (int j = 0; j < k; ++j) P->mem[slot_off + j * B.m + i] = inv_rank[a[j]];
     }
     if (k > 1) B.fp32_ok = fp32_scale(r, k, &B.qexp32);
-    // generic-kernel stack placement: LDS if a 64-thread block needs <= 64 KiB
-    if (k >= 4) {
-      const int W = r - k + 1;
-      const int64_t per64 = 16LL * k + (int64_t)(k - 3) * W * 8;
-      const int64_t per32 = 16LL * k + (int64_t)(k - 3) * W * 4;
-      B.lds64 = per64 * kGenBlock <= 65536 ? 1 : 0;
-      B.lds32 = per32 * kGenBlock <= 65536 ? 1 : 0;
-    }
     P->buckets.push_back(B);
     edge_off += B.m;
     slot_off += (int64_t)k * B.m;
@@ -347,7 +344,12 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
     return code;
   };
   if ((rc = upload(&P->d_mem, P->mem.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
-  if ((rc = upload(&P->d_tslot, P->tslot.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  {
+    // node-major position of every member slot: pos[tslot[q]] = q
+    std::vector<int32_t> pos(nnz);
+    for (int64_t q = 0; q < nnz; ++q) pos[P->tslot[q]] = static_cast<int32_t>(q);
+    if ((rc = upload(&P->d_pos, pos.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  }
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   for (size_t l = 0; l < hl.size(); ++l) {
     ReduceLevel L;
@@ -364,21 +366,89 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
       P->d_partials.push_back(part);
     }
   }
+  // ---- kernel selection, bucket descriptors, fused generic groups
+  const EdgeTables& tab = edge_tables();
   for (Bucket& B : P->buckets) {
-    if (B.k < 4) continue;
     const int W = r - B.k + 1;
-    const size_t scal = 2 * (size_t)B.k * B.m * sizeof(double);
-    if (!B.lds64) {
-      const size_t bytes = scal + (size_t)(B.k - 3) * W * B.m * sizeof(double);
-      if (hipMalloc(&B.gstack64, bytes) != hipSuccess) return fail(STTSV_ENOMEM);
-      P->device_bytes += (int64_t)bytes;
-    }
-    if (!B.lds32 && B.fp32_ok) {
-      const size_t bytes = scal + (size_t)(B.k - 3) * W * B.m * sizeof(float);
-      if (hipMalloc(&B.gstack32, bytes) != hipSuccess) return fail(STTSV_ENOMEM);
-      P->device_bytes += (int64_t)bytes;
+    for (int t = 0; t < 2; ++t) {
+      BucketDesc& d = B.desc[t];
+      d.mem = P->d_mem + B.slot_off;
+      d.pos = P->d_pos + B.slot_off;
+      d.gstack = nullptr;
+      d.m = B.m;
+      d.k = B.k;
+      d.r = r;
+      d.W = W;
+      d.qexp = t == 1 ? B.qexp32 : 0;
+      d.lds_stack = 1;
+      d.pad = 0;
+      d.wk = P->weights[B.k];
+      const auto& small = t == 0 ? tab.small64 : tab.small32;
+      int kind = -1;
+      if (B.k == 2) kind = SK_K2;
+      if (B.k == 3) kind = SK_K3;
+      if (B.k >= 4 && B.k <= 7 && !(P->flags & STTSV_FLAG_GENERIC_ONLY) && small[SK_R4 + (B.k - 4)][W] != nullptr)
+        kind = SK_R4 + (B.k - 4);
+      B.small_kind[t] = kind;
     }
   }
+  for (int seq = 0; seq < 2; ++seq) {
+    for (int rg = 0; rg < kGenRanges; ++rg) {
+      for (int t = 0; t < 2; ++t) {
+        GenGroup G;
+        G.range = rg;
+        G.seq = seq;
+        G.f64 = t == 0;
+        for (size_t b = 0; b < P->buckets.size(); ++b) {
+          const Bucket& B = P->buckets[b];
+          const int type = (seq == 0 || !B.fp32_ok || B.k == 1) ? 0 : 1;
+          if (type != t || B.k < 4 || B.small_kind[t] >= 0) continue;
+          if (gen_range_of(r - B.k + 1) != rg) continue;
+          G.buckets.push_back(static_cast<int>(b));
+        }
+        if (G.buckets.empty()) continue;
+        // longest per-edge work first, so the slow blocks start early
+        std::stable_sort(G.buckets.begin(), G.buckets.end(), [&](int a, int b) {
+          const Bucket& A = P->buckets[a];
+          const Bucket& B = P->buckets[b];
+          const int64_t wa = (int64_t)(A.k - 3) * (r - A.k + 1) * (r - A.k + 1);
+          const int64_t wb = (int64_t)(B.k - 3) * (r - B.k + 1) * (r - B.k + 1);
+          return wa > wb;
+        });
+        const size_t tsz = t == 0 ? sizeof(double) : sizeof(float);
+        std::vector<BucketDesc> bks;
+        std::vector<GenTask> tasks;
+        for (size_t q = 0; q < G.buckets.size(); ++q) {
+          Bucket& B = P->buckets[G.buckets[q]];
+          const int W = r - B.k + 1;
+          const int64_t need = (int64_t)kGenBlock * (16LL * B.k + (int64_t)(B.k - 3) * W * (int64_t)tsz);
+          BucketDesc& d = B.desc[t];
+          if (need <= kLdsBudget) {
+            d.lds_stack = 1;
+            G.lds = std::max(G.lds, static_cast<size_t>(need));
+          } else {
+            d.lds_stack = 0;
+            if (B.gstack[t] == nullptr) {
+              const size_t bytes = 2 * (size_t)B.k * B.m * sizeof(double) + (size_t)(B.k - 3) * W * B.m * tsz;
+              if (hipMalloc(&B.gstack[t], bytes) != hipSuccess) return fail(STTSV_ENOMEM);
+              P->device_bytes += (int64_t)bytes;
+            }
+            d.gstack = B.gstack[t];
+          }
+          bks.push_back(d);
+          const int64_t nblk = (B.m + kGenBlock - 1) / kGenBlock;
+          for (int64_t blk = 0; blk < nblk; ++blk)
+            tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
+        }
+        G.ntasks = (int64_t)tasks.size();
+        P->groups.push_back(std::move(G));
+        GenGroup& H = P->groups.back();
+        if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
+        if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
+      }
+    }
+  }
+  build_stages(*P);
   if (hipDeviceSynchronize() != hipSuccess) return fail(STTSV_EHIP);
   *out = P;
   return STTSV_OK;

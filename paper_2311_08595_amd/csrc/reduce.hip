@@ -1,54 +1,71 @@
 // Deterministic node-major reduction y_v = sum of v's per-incidence
 // contributions (replaces the AtomicAdd accumulation of Alg. 3 / Alg. 4).
+// The edge kernels store every contribution at its node-major position, so
+// each vertex's terms are contiguous here.
 //
-// The summation tree of every vertex is fixed by its degree alone: the
-// incidences of v, in canonical edge order, are cut into chunks of kChunk
-// consecutive terms summed left to right; if there is more than one chunk,
-// the chunk sums form the input of the next level and are cut the same way.
-// So y is bitwise identical across runs, launch shapes and devices.
+// The summation tree of every vertex is fixed by its incidence list alone:
+// the list (canonical edge order) is cut into chunks of kChunk = 32
+// consecutive terms.  A chunk is summed by a group of 8 lanes: lane j adds
+// terms j, j+8, j+16, j+24 in that order (missing terms are exact zeros),
+// then the 8 lane sums are combined by a halving butterfly (offsets 4, 2, 1).
+// If a vertex has more than one chunk, the chunk sums are the input of the
+// next level and are cut the same way.  No launch parameter enters the tree,
+// so y is bitwise identical across runs, launch shapes and devices.
 #include "internal.hpp"
 
 namespace sttsv {
 namespace {
 
-template <bool GATHER>
+constexpr int kGroup = 8;                   // lanes per chunk
+constexpr int kPerLane = kChunk / kGroup;   // terms per lane
+static_assert(kChunk % kGroup == 0, "chunk must split evenly over the group");
+
 __global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ len,
                                                     const int32_t* __restrict__ dst, int64_t nchunks,
                                                     const double* __restrict__ in,
-                                                    const int32_t* __restrict__ tslot,
                                                     double* __restrict__ y, double* __restrict__ next,
                                                     const int32_t* done) {
-  if (done != nullptr && *done) return;
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= nchunks) return;
-  const int32_t s = start[c];
-  const int32_t l = len[c];
-  double acc = 0.0;
-  if (l > 0) {
-    acc = GATHER ? in[tslot[s]] : in[s];
-    for (int32_t p = 1; p < l; ++p) acc += GATHER ? in[tslot[s + p]] : in[s + p];
+  if (done != nullptr && *done) return;     // uniform: every lane leaves together
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c = gid / kGroup;
+  const int j = static_cast<int>(gid % kGroup);
+  int32_t s = 0, l = 0;
+  if (c < nchunks) {
+    s = start[c];
+    l = len[c];
   }
-  const int32_t d = dst[c];
-  if (d >= 0)
-    y[d] = acc;
-  else
-    next[-(int64_t)d - 1] = acc;
+  int32_t idx[kPerLane];
+#pragma unroll
+  for (int q = 0; q < kPerLane; ++q) {
+    const int p = j + q * kGroup;
+    idx[q] = p < l ? s + p : -1;
+  }
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPerLane; ++q)
+    if (idx[q] >= 0) v += in[idx[q]];
+  v += __shfl_down(v, 4, kGroup);
+  v += __shfl_down(v, 2, kGroup);
+  v += __shfl_down(v, 1, kGroup);
+  if (j == 0 && c < nchunks) {
+    const int32_t d = dst[c];
+    if (d >= 0)
+      y[d] = v;
+    else
+      next[-(int64_t)d - 1] = v;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_reduce_level(const ReduceLevel& L, int level, const double* in,
-                               const int32_t* tslot, double* y, double* next,
+hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
                                const int32_t* done, hipStream_t s) {
   if (L.nchunks == 0) return hipSuccess;
-  const dim3 grid(static_cast<unsigned>((L.nchunks + 255) / 256));
-  if (level == 0)
-    hipLaunchKernelGGL((reduce_level<true>), grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst,
-                       L.nchunks, in, tslot, y, next, done);
-  else
-    hipLaunchKernelGGL((reduce_level<false>), grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst,
-                       L.nchunks, in, tslot, y, next, done);
+  const int64_t threads = L.nchunks * kGroup;
+  const dim3 grid(static_cast<unsigned>((threads + 255) / 256));
+  hipLaunchKernelGGL(reduce_level, grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst, L.nchunks, in, y,
+                     next, done);
   return hipGetLastError();
 }
 

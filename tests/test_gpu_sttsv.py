@@ -195,3 +195,19 @@ def test_degree_invariant_large(torch_cuda, prec):
     d = np.bincount(w["eidx"], minlength=w["n"]).astype(float)
     y = _apply(torch_cuda, w["eptr"], w["eidx"], w["n"], w["r"], np.ones(w["n"]), prec)
     assert _relerr(y, d) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kernel_variants_bitwise_equal(torch_cuda, prec):
+    # register-resident and generic edge kernels compute the same operations
+    # in the same order: contributions, hence y, must agree bit for bit
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    for r in (9, 25, 50):
+        eptr, eidx, x = _mixed(30 + r, 2000, 12000, r, 4, 8)
+        xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+        with st.Plan(eptr, eidx, 2000, r) as p1, st.Plan(eptr, eidx, 2000, r, flags=_lib.FLAG_GENERIC_ONLY) as p2:
+            a = p1.apply(xd, precision=prec).cpu().numpy()
+            b = p2.apply(xd, precision=prec).cpu().numpy()
+        assert a.tobytes() == b.tobytes(), r

@@ -28,6 +28,17 @@ constexpr int kGenLo[kGenRanges] = {1, 9, 17, 25, 33, 41, 49, 57};
 constexpr int kGenHi[kGenRanges] = {8, 16, 24, 32, 40, 48, 56, 63};
 constexpr int64_t kLdsBudget = 40 * 1024;  // LDS per generic block (>= 4 blocks per CU)
 
+// Generic kernel: suffix checkpoint interval C for window W and series size
+// tsz bytes (C + 2 live series within about 160 VGPRs, at most 4), and the
+// per-thread stack it needs (z values and suffix products of z in FP64, then
+// one checkpoint series per C forward steps).
+constexpr int kg_checkpoint(int W, int tsz) {
+  return (640 / (W * tsz) - 2) >= 4 ? 4 : (640 / (W * tsz) - 2) >= 1 ? (640 / (W * tsz) - 2) : 1;
+}
+constexpr int64_t kg_stack_bytes(int k, int W, int tsz) {
+  return 16LL * k + (int64_t)((k - 3 + kg_checkpoint(W, tsz) - 1) / kg_checkpoint(W, tsz)) * W * tsz;
+}
+
 inline int gen_range_of(int W) {
   for (int g = 0; g < kGenRanges; ++g)
     if (W >= kGenLo[g] && W <= kGenHi[g]) return g;

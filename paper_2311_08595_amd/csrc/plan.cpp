@@ -421,7 +421,7 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
         for (size_t q = 0; q < G.buckets.size(); ++q) {
           Bucket& B = P->buckets[G.buckets[q]];
           const int W = r - B.k + 1;
-          const int64_t need = (int64_t)kGenBlock * (16LL * B.k + (int64_t)(B.k - 3) * W * (int64_t)tsz);
+          const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, static_cast<int>(tsz));
           BucketDesc& d = B.desc[t];
           if (need <= kLdsBudget) {
             d.lds_stack = 1;
@@ -429,7 +429,7 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
           } else {
             d.lds_stack = 0;
             if (B.gstack[t] == nullptr) {
-              const size_t bytes = 2 * (size_t)B.k * B.m * sizeof(double) + (size_t)(B.k - 3) * W * B.m * tsz;
+              const size_t bytes = (size_t)kg_stack_bytes(B.k, W, static_cast<int>(tsz)) * (size_t)B.m;
               if (hipMalloc(&B.gstack[t], bytes) != hipSuccess) return fail(STTSV_ENOMEM);
               P->device_bytes += (int64_t)bytes;
             }

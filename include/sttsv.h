@@ -179,22 +179,77 @@ int heigvec_solve_ex(sttsv_plan_t plan, const double* x0, double tol,
                      const sttsv_solve_opts* opts, double* x_out,
                      sttsv_solve_info* info);
 
+/* ---- many hypergraphs in one plan -------------------------------------- */
+
+/* One hypergraph of a batch (host CSR, same rules as sttsv_plan's arguments;
+ * each graph has its own vertex count n and tensor order r). */
+typedef struct {
+    const int64_t* eptr;
+    const int32_t* eidx;
+    int64_t m;
+    int32_t n;
+    int32_t r;
+} sttsv_graph_desc;
+
+/*
+ * sttsv_plan_batch -- one plan over G hypergraphs (their disjoint union).
+ *
+ * Graph g's vertices are numbered after those of graphs 0..g-1: vectors
+ * passed to sttsv_apply / heigvec_solve_batch on a batch plan are the
+ * concatenation of the per-graph vectors in graph order (offsets from
+ * sttsv_plan_graph_info).  Edges of all graphs share the edge-kernel
+ * launches (buckets keyed by (r, |e|)), and every graph's y is bitwise
+ * identical to what a single-graph plan of it returns.
+ *   G    >= 1;  gs  host, G descriptors (copied);  opts, out as sttsv_plan.
+ * Errors: as sttsv_plan, for any graph.
+ */
+int sttsv_plan_batch(int32_t G, const sttsv_graph_desc* gs, const sttsv_opts* opts,
+                     sttsv_plan_t* out);
+
+/*
+ * heigvec_solve_batch -- Alg. 1 for every graph of a plan at once, in one
+ * captured hipGraph per check_every iterations; a graph that meets its test
+ * is masked (its edges skipped, its x frozen) while the others go on.
+ *   x0     device, concatenated double[n_total] warm starts, or NULL (uniform).
+ *   x_out  device, concatenated double[n_total]; each graph's slice has l1 norm 1.
+ *   infos  host, G entries (nullable).
+ * Returns the worst per-graph status (EINVAL > ENUMERIC > ENOTCONV > OK);
+ * EDISCONNECTED if any graph is not connected.  Synchronous.
+ */
+int heigvec_solve_batch(sttsv_plan_t plan, const double* x0, double tol,
+                        const sttsv_solve_opts* opts, double* x_out,
+                        sttsv_solve_info* infos);
+
+/* Vertex offset, vertex count, edge count, order and connectivity of graph g. */
+typedef struct {
+    int64_t m;
+    int32_t n, r, voff, connected;
+} sttsv_graph_info;
+
+int sttsv_plan_graph_info(sttsv_plan_t plan, int32_t g, sttsv_graph_info* info);
+
 /* ---- plan introspection (host copies; used to check the layout) ------- */
 #define STTSV_Q_PERM        0  /* int64[m]   input index of canonical edge c      */
 #define STTSV_Q_MEM         1  /* int64[nnz] member slots (original vertex ids)   */
-#define STTSV_Q_BUCKET_K    2  /* int64[nb]  edge size of each bucket             */
+#define STTSV_Q_BUCKET_K    2  /* int64[nb]  edge size of each bucket (buckets are  */
+                               /*            ordered by (r, k); see BUCKET_R)      */
 #define STTSV_Q_BUCKET_M    3  /* int64[nb]  edge count of each bucket            */
 #define STTSV_Q_TPTR        4  /* int64[n+1] node-major offsets                   */
 #define STTSV_Q_TSLOT       5  /* int64[nnz] node-major slot lists                */
 #define STTSV_Q_WEIGHTS     6  /* double[r+1] w/|beta| (r-1)! per size (index k)  */
 #define STTSV_Q_SCALE_EXP   7  /* int64[r+1]  FP32 series scale exponent per size */
-                               /*             (INT32_MIN: size runs in FP64)      */
+                               /*             (INT32_MIN: size runs in FP64), for */
+                               /*             the first graph's order r           */
+#define STTSV_Q_BUCKET_R    8  /* int64[nb]  tensor order of each bucket          */
 
-/* Sizes of the plan: m, n, r, nnz, number of buckets, connected flag. */
+/* Sizes of the plan: m, n, largest r, nnz, number of buckets, number of
+ * graphs, connected flag (all graphs). */
 typedef struct {
     int64_t m, nnz;
     int32_t n, r, nbuckets, connected;
     int64_t device_bytes;  /* device memory held by the plan                     */
+    int32_t graphs;
+    int32_t reserved;
 } sttsv_plan_info;
 
 int sttsv_plan_get_info(sttsv_plan_t plan, sttsv_plan_info* info);

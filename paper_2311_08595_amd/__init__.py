@@ -31,26 +31,79 @@ def _dev_ptr(t, n, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
-class Plan:
-    """Execution plan of one hypergraph (``sttsv_plan``)."""
+def _opts(precision, flags, stream):
+    import torch
+    if stream is None and torch.cuda.is_available():
+        stream = torch.cuda.current_stream()
+    sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    return _lib.SttsvOpts(_lib.PREC[precision], int(flags), sptr), stream
 
-    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None, flags=0):
-        import torch
+
+def _info_dict(info, rc):
+    return dict(iterations=info.iterations, iters_fp32=info.iters_fp32, iters_fp64=info.iters_fp64,
+                converged=bool(info.converged), lambda_min=info.lambda_min,
+                lambda_max=info.lambda_max, criterion=info.criterion, status=rc)
+
+
+class Plan:
+    """Execution plan of one hypergraph (``sttsv_plan``), or of several
+    (``Plan.batch`` -> ``sttsv_plan_batch``)."""
+
+    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None, flags=0, _graphs=None):
         lib = _lib.load()
         self._lib = lib
-        eptr = np.ascontiguousarray(eptr, dtype=np.int64)
-        eidx = np.ascontiguousarray(eidx, dtype=np.int32)
-        self.n, self.r, self.m = int(n), int(r), len(eptr) - 1
-        if stream is None and torch.cuda.is_available():
-            stream = torch.cuda.current_stream()
-        sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
-        self.stream = stream
-        opts = _lib.SttsvOpts(_lib.PREC[precision], int(flags), sptr)
+        opts, self.stream = _opts(precision, flags, stream)
         h = ctypes.c_void_p()
-        _lib.check(lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, self.m, self.n, self.r,
-                                  ctypes.byref(opts), ctypes.byref(h)))
+        if _graphs is None:
+            eptr = np.ascontiguousarray(eptr, dtype=np.int64)
+            eidx = np.ascontiguousarray(eidx, dtype=np.int32)
+            self.n, self.r, self.m = int(n), int(r), len(eptr) - 1
+            _lib.check(lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, self.m, self.n, self.r,
+                                      ctypes.byref(opts), ctypes.byref(h)))
+            self.graphs = 1
+        else:
+            keep = []
+            descs = (_lib.GraphDesc * len(_graphs))()
+            for g, (ep, ei, ng, rg) in enumerate(_graphs):
+                ep = np.ascontiguousarray(ep, dtype=np.int64)
+                ei = np.ascontiguousarray(ei, dtype=np.int32)
+                keep.append((ep, ei))
+                descs[g] = _lib.GraphDesc(ep.ctypes.data, ei.ctypes.data, len(ep) - 1, int(ng), int(rg))
+            _lib.check(lib.sttsv_plan_batch(len(_graphs), descs, ctypes.byref(opts), ctypes.byref(h)))
+            self.n = sum(int(g[2]) for g in _graphs)
+            self.m = sum(len(g[0]) - 1 for g in _graphs)
+            self.r = max(int(g[3]) for g in _graphs)
+            self.graphs = len(_graphs)
         self._h = h
         self.precision = precision
+
+    @classmethod
+    def batch(cls, graphs, precision="fp64", stream=None, flags=0):
+        """One plan over many hypergraphs: ``graphs`` = [(eptr, eidx, n, r), ...].
+        Vectors are the concatenation of the per-graph vectors in graph order."""
+        return cls(None, None, None, None, precision, stream, flags, _graphs=list(graphs))
+
+    def graph_info(self, g):
+        gi = _lib.GraphInfo()
+        _lib.check(self._lib.sttsv_plan_graph_info(self._h, int(g), ctypes.byref(gi)))
+        return dict(m=gi.m, n=gi.n, r=gi.r, voff=gi.voff, connected=bool(gi.connected))
+
+    def solve_batch(self, tol=1e-8, x0=None, out=None, max_iter=500, check_every=8, schedule="fp64",
+                    use_graph=True, shift=0.0, switch_tol=1e-6, raise_on_notconv=True):
+        """Alg. 1 for every graph of the plan at once.  Returns (x, [info per graph])."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        op = _dev_ptr(out, self.n, "out")
+        x0p = None if x0 is None else _dev_ptr(x0, self.n, "x0")
+        o = _lib.SolveOpts(max_iter, check_every, _lib.SCHEDULE[schedule], 1 if use_graph else 0,
+                           float(shift), float(switch_tol))
+        infos = (_lib.SolveInfo * self.graphs)()
+        rc = self._lib.heigvec_solve_batch(self._h, x0p, float(tol), ctypes.byref(o), op, infos)
+        res = [_info_dict(infos[g], rc) for g in range(self.graphs)]
+        if rc != _lib.STTSV_OK and (rc != _lib.STTSV_ENOTCONV or raise_on_notconv):
+            _lib.check(rc)
+        return out, res
 
     # ------------------------------------------------------------ compute
     def apply(self, x, y=None, precision=None):
@@ -76,9 +129,7 @@ class Plan:
                            float(shift), float(switch_tol))
         info = _lib.SolveInfo()
         rc = self._lib.heigvec_solve_ex(self._h, x0p, float(tol), ctypes.byref(o), op, ctypes.byref(info))
-        d = dict(iterations=info.iterations, iters_fp32=info.iters_fp32, iters_fp64=info.iters_fp64,
-                 converged=bool(info.converged), lambda_min=info.lambda_min,
-                 lambda_max=info.lambda_max, criterion=info.criterion, status=rc)
+        d = _info_dict(info, rc)
         if rc != _lib.STTSV_OK and (rc != _lib.STTSV_ENOTCONV or raise_on_notconv):
             _lib.check(rc)
         return out, d
@@ -88,14 +139,15 @@ class Plan:
         pi = _lib.PlanInfo()
         _lib.check(self._lib.sttsv_plan_get_info(self._h, ctypes.byref(pi)))
         return dict(m=pi.m, nnz=pi.nnz, n=pi.n, r=pi.r, nbuckets=pi.nbuckets,
-                    connected=bool(pi.connected), device_bytes=pi.device_bytes)
+                    connected=bool(pi.connected), device_bytes=pi.device_bytes, graphs=pi.graphs)
 
     def query(self, what):
         inf = self.info()
         sizes = {_lib.Q_PERM: inf["m"], _lib.Q_MEM: inf["nnz"], _lib.Q_BUCKET_K: inf["nbuckets"],
                  _lib.Q_BUCKET_M: inf["nbuckets"], _lib.Q_TPTR: inf["n"] + 1,
-                 _lib.Q_TSLOT: inf["nnz"], _lib.Q_WEIGHTS: inf["r"] + 1,
-                 _lib.Q_SCALE_EXP: inf["r"] + 1}
+                 _lib.Q_TSLOT: inf["nnz"], _lib.Q_BUCKET_R: inf["nbuckets"]}
+        if what in (_lib.Q_WEIGHTS, _lib.Q_SCALE_EXP):
+            sizes[what] = self.graph_info(0)["r"] + 1
         cnt = sizes[what]
         out = np.empty(cnt, dtype=np.float64 if what == _lib.Q_WEIGHTS else np.int64)
         _lib.check(self._lib.sttsv_plan_query(self._h, what, out.ctypes.data, cnt))

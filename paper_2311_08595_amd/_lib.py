@@ -26,11 +26,12 @@ FLAG_GENERIC_ONLY = 1
 PREC = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"fp64": 0, "fp32_fp64": 1}
 
-Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP = range(8)
+Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, Q_BUCKET_R = range(9)
 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
-           "heigvec_solve", "heigvec_solve_ex",
+           "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
+           "sttsv_plan_graph_info",
            "sttsv_plan_get_info", "sttsv_plan_query", "sttsv_plan_destroy", "sttsv_strerror"]
 
 
@@ -55,7 +56,17 @@ class SolveInfo(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n", ctypes.c_int32),
                 ("r", ctypes.c_int32), ("nbuckets", ctypes.c_int32), ("connected", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("eptr", ctypes.c_void_p), ("eidx", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("n", ctypes.c_int32), ("r", ctypes.c_int32)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int32), ("r", ctypes.c_int32),
+                ("voff", ctypes.c_int32), ("connected", ctypes.c_int32)]
 
 
 class SttsvError(RuntimeError):
@@ -85,6 +96,9 @@ def load(path=None):
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]
     lib.heigvec_solve_ex.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]
+    lib.sttsv_plan_batch.argtypes = [i32, P, ctypes.POINTER(SttsvOpts), ctypes.POINTER(P)]
+    lib.heigvec_solve_batch.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, P]
+    lib.sttsv_plan_graph_info.argtypes = [P, i32, ctypes.POINTER(GraphInfo)]
     lib.sttsv_plan_get_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.sttsv_plan_query.argtypes = [P, i32, P, i64]
     lib.sttsv_plan_destroy.argtypes = [P]

@@ -43,11 +43,38 @@ int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
   if (out == nullptr) return STTSV_EINVAL;
   return guarded([&] {
     Plan* p = nullptr;
-    const int rc = sttsv::build_plan(eptr, eidx, m, n, r, opts, &p);
+    const sttsv::GraphIn g{eptr, eidx, m, n, r};
+    const int rc = sttsv::build_plan(1, &g, opts, &p);
     if (rc != STTSV_OK) return rc;
     *out = new sttsv_plan_s{p};
     return STTSV_OK;
   });
+}
+
+int sttsv_plan_batch(int32_t G, const sttsv_graph_desc* gs, const sttsv_opts* opts, sttsv_plan_t* out) {
+  if (out == nullptr || gs == nullptr || G < 1) return STTSV_EINVAL;
+  return guarded([&] {
+    std::vector<sttsv::GraphIn> in(G);
+    for (int g = 0; g < G; ++g) in[g] = sttsv::GraphIn{gs[g].eptr, gs[g].eidx, gs[g].m, gs[g].n, gs[g].r};
+    Plan* p = nullptr;
+    const int rc = sttsv::build_plan(G, in.data(), opts, &p);
+    if (rc != STTSV_OK) return rc;
+    *out = new sttsv_plan_s{p};
+    return STTSV_OK;
+  });
+}
+
+int sttsv_plan_graph_info(sttsv_plan_t plan, int32_t g, sttsv_graph_info* info) {
+  if (plan == nullptr || plan->p == nullptr || info == nullptr) return STTSV_EINVAL;
+  const Plan& p = *plan->p;
+  if (g < 0 || g >= (int32_t)p.graphs.size()) return STTSV_EINVAL;
+  const sttsv::GraphInfo& I = p.graphs[g];
+  info->m = I.m;
+  info->n = I.n;
+  info->r = I.r;
+  info->voff = I.voff;
+  info->connected = I.connected ? 1 : 0;
+  return STTSV_OK;
 }
 
 int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t precision) {
@@ -107,7 +134,22 @@ int heigvec_solve_ex(sttsv_plan_t plan, const double* x0, double tol, const stts
   o.shift = 0.0;
   o.switch_tol = 1e-6;
   if (opts != nullptr) o = *opts;
+  if (plan->p->graphs.size() != 1) return STTSV_EINVAL;   // batches: heigvec_solve_batch
   return guarded([&] { return sttsv::solve(*plan->p, x0, tol, o, x_out, info); });
+}
+
+int heigvec_solve_batch(sttsv_plan_t plan, const double* x0, double tol, const sttsv_solve_opts* opts,
+                        double* x_out, sttsv_solve_info* infos) {
+  if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
+  sttsv_solve_opts o;
+  o.max_iter = 500;
+  o.check_every = 8;
+  o.schedule = STTSV_SOLVE_FP64;
+  o.use_graph = 1;
+  o.shift = 0.0;
+  o.switch_tol = 1e-6;
+  if (opts != nullptr) o = *opts;
+  return guarded([&] { return sttsv::solve(*plan->p, x0, tol, o, x_out, infos); });
 }
 
 int heigvec_solve(sttsv_plan_t plan, const double* x0, double tol, double* x_out, sttsv_solve_info* info) {
@@ -124,6 +166,8 @@ int sttsv_plan_get_info(sttsv_plan_t plan, sttsv_plan_info* info) {
   info->nbuckets = static_cast<int32_t>(p.buckets.size());
   info->connected = p.connected ? 1 : 0;
   info->device_bytes = p.device_bytes;
+  info->graphs = static_cast<int32_t>(p.graphs.size());
+  info->reserved = 0;
   return STTSV_OK;
 }
 
@@ -141,17 +185,20 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
       case STTSV_Q_TSLOT:
         return copy_out<int32_t, int64_t>(p.tslot, out, count);
       case STTSV_Q_BUCKET_K:
-      case STTSV_Q_BUCKET_M: {
+      case STTSV_Q_BUCKET_M:
+      case STTSV_Q_BUCKET_R: {
         std::vector<int64_t> v;
-        for (const auto& b : p.buckets) v.push_back(what == STTSV_Q_BUCKET_K ? b.k : b.m);
+        for (const auto& b : p.buckets)
+          v.push_back(what == STTSV_Q_BUCKET_K ? b.k : what == STTSV_Q_BUCKET_M ? b.m : b.r);
         return copy_out<int64_t, int64_t>(v, out, count);
       }
       case STTSV_Q_WEIGHTS:
         return copy_out<double, double>(p.weights, out, count);
       case STTSV_Q_SCALE_EXP: {
-        std::vector<int64_t> v(p.r + 1, INT32_MIN);
+        const int r0 = p.graphs[0].r;
+        std::vector<int64_t> v(r0 + 1, INT32_MIN);
         for (const auto& b : p.buckets)
-          if (b.k > 1 && b.fp32_ok) v[b.k] = b.qexp32;
+          if (b.r == r0 && b.k > 1 && b.fp32_ok) v[b.k] = b.qexp32;
         return copy_out<int64_t, int64_t>(v, out, count);
       }
       default:

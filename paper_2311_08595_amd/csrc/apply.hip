@@ -29,6 +29,7 @@ __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   if (c.done != nullptr && *c.done) return;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= b.m) return;
+  if (c.gskip != nullptr && c.gskip[b.gid != nullptr ? b.gid[i] : 0]) return;
   const double xv = c.x[b.mem[i]];
   int e2 = 0;
   const double f = frexp(xv, &e2);          // xv = f 2^e2
@@ -91,11 +92,8 @@ int stage_count(const Plan& p, int precision) {
   return static_cast<int>(p.stages[precision == STTSV_PREC_FP32 ? 1 : 0].size());
 }
 
-hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int precision,
-                        const int32_t* done, hipStream_t s) {
-  const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
+static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, double* y, hipStream_t s) {
   const EdgeTables& tab = edge_tables();
-  const EdgeCall c{x, p.d_contrib, done};
   if (S.type == 0) {
     const Bucket& B = p.buckets[S.index];
     const BucketDesc& d = B.desc[S.f64 ? 0 : 1];
@@ -111,7 +109,13 @@ hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int prec
   const size_t l = static_cast<size_t>(S.index);
   const double* in = l == 0 ? p.d_contrib : p.d_partials[l - 1];
   double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
-  return launch_reduce_level(p.levels[l], in, y, next, done, s);
+  return launch_reduce_level(p.levels[l], in, y, next, c.done, s);
+}
+
+hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int precision,
+                        const int32_t* done, hipStream_t s) {
+  const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
+  return launch_stage_call(p, S, EdgeCall{x, p.d_contrib, done, nullptr}, y, s);
 }
 
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
@@ -119,6 +123,27 @@ hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
   const int ns = stage_count(p, precision);
   for (int t = 0; t < ns; ++t) {
     const hipError_t e = launch_stage(p, t, x, y, precision, done, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
+                        hipStream_t s) {
+  const EdgeCall c{x, p.d_contrib, done, gskip};
+  for (const Stage& S : p.stages[precision == STTSV_PREC_FP32 ? 1 : 0]) {
+    if (S.type == 2) continue;
+    const hipError_t e = launch_stage_call(p, S, c, nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s) {
+  const EdgeCall c{nullptr, p.d_contrib, done, nullptr};
+  for (const Stage& S : p.stages[0]) {
+    if (S.type != 2) continue;
+    const hipError_t e = launch_stage_call(p, S, c, y, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -49,7 +49,8 @@ inline int gen_range_of(int W) {
 struct EdgeCall {
   const double* x;      // input vector
   double* contrib;      // per-incidence contributions, node-major order
-  const int32_t* done;  // early-exit flag (solver), nullable
+  const int32_t* done;  // whole launch is skipped when *done != 0 (nullable)
+  const int32_t* gskip; // per-graph skip flags indexed by BucketDesc::gid (nullable)
 };
 
 // Plan-time description of one size bucket (device pointers offset to the
@@ -57,6 +58,7 @@ struct EdgeCall {
 struct BucketDesc {
   const int32_t* mem;   // member ids, SoA: mem[j*m + i]
   const int32_t* pos;   // node-major position of each member slot, same layout
+  const int32_t* gid;   // graph of each edge (batched plans), or null
   void* gstack;         // generic kernel: per-edge global stack (when not in LDS)
   int64_t m;            // edges in the bucket
   int32_t k, r, W;      // edge size, tensor order, series window r - k + 1
@@ -95,6 +97,7 @@ struct ReduceLevel {
 };
 
 struct Bucket {
+  int32_t r = 0;          // tensor order of the graphs in this bucket
   int32_t k = 0;
   int64_t m = 0;
   int64_t edge_off = 0;   // first canonical edge
@@ -126,9 +129,19 @@ struct Stage {
   bool f64;      // series type of an edge stage
 };
 
-struct Plan {
+// One hypergraph of a (possibly batched) plan.
+struct GraphInfo {
   int64_t m = 0, nnz = 0;
   int32_t n = 0, r = 0;
+  int32_t voff = 0;       // first vertex in the plan's vertex numbering
+  int64_t eoff = 0;       // first input edge in the plan's edge numbering
+  bool connected = false;
+};
+
+struct Plan {
+  int64_t m = 0, nnz = 0;
+  int32_t n = 0, r = 0;   // r: the largest tensor order of the plan's graphs
+  std::vector<GraphInfo> graphs;
   int32_t precision = STTSV_PREC_FP64;
   int32_t flags = 0;
   hipStream_t stream = nullptr;
@@ -136,8 +149,8 @@ struct Plan {
   bool connected = false;
   int64_t device_bytes = 0;
 
-  std::vector<Bucket> buckets;
-  std::vector<double> weights;      // index k = 0..r
+  std::vector<Bucket> buckets;      // ordered by (r, k)
+  std::vector<double> weights;      // w/|beta| (r-1)! for k = 0..r of the first graph's r
 
   // host copies of the canonical layout (introspection)
   std::vector<int64_t> perm;
@@ -148,6 +161,7 @@ struct Plan {
   // device buffers
   int32_t* d_mem = nullptr;
   int32_t* d_pos = nullptr;       // node-major position of every member slot
+  int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
   double* d_contrib = nullptr;    // node-major contributions
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
   std::vector<Stage> stages[2];   // launch sequence per precision [fp64, fp32]
@@ -158,9 +172,14 @@ struct Plan {
   struct Solver* solver = nullptr;
 };
 
-// planner (plan.cpp)
-int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, int32_t r,
-               const sttsv_opts* opts, Plan** out);
+// planner (plan.cpp): a plan over the disjoint union of G hypergraphs
+struct GraphIn {
+  const int64_t* eptr;
+  const int32_t* eidx;
+  int64_t m;
+  int32_t n, r;
+};
+int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out);
 void free_plan(Plan* p);
 
 // STTSV launch sequence (apply.hip): per-bucket edge kernels and fused
@@ -172,14 +191,20 @@ hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int prec
                         const int32_t* done, hipStream_t s);
 void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t* size, int64_t* count);
 void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
+// The edge launches of one precision (per-graph skip flags, nullable), and
+// the reduction alone: the solver runs both precisions' edge launches then
+// one reduction per iteration.
+hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
+                        hipStream_t s);
+hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s);
 
 // reduction kernels (reduce.hip)
 hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
                                const int32_t* done, hipStream_t s);
 
-// solver (nqz.hip)
+// solver (nqz.hip): every graph of the plan; infos has one entry per graph
 int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, double* x_out,
-          sttsv_solve_info* info);
+          sttsv_solve_info* infos);
 void free_solver(Plan& p);
 
 }  // namespace sttsv

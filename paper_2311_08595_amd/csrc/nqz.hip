@@ -1,51 +1,67 @@
-// NQZ iteration (Alg. 1) on the GPU.
+// NQZ iteration (Alg. 1) on the GPU, for every hypergraph of a plan at once.
 //
-// Every step of an iteration is a kernel whose decisions live in a device
-// control block, so K iterations can be captured once in a hipGraph and
-// replayed; the host only reads the control block between replays.
+// Every step of an iteration is a kernel whose decisions live in device
+// control blocks (one per graph plus one per solve), so K iterations can be
+// captured once in a hipGraph and replayed; the host only reads the solve's
+// "all done" flag between replays.
 //
-// Iteration t (x~ = current iterate scaled to max 1):
+// Iteration t for graph g (x~ = its current iterate scaled to max 1):
 //   z = TTSV1(x~)                            edge kernels + node reduction
 //   z' = z + alpha x~^[r-1]                  optional shift (alpha = 0: Alg. 1)
-//   lambda_v = z'_v / x~_v^(r-1)             min / max over v
-//   crit = (lambda_max - lambda_min) / lambda_min;  stop if crit < tol
+//   lambda_v = z'_v / x~_v^(r-1)             min / max over g's vertices
+//   crit = (lambda_max - lambda_min) / lambda_min;  g stops when crit < tol
 //   w = z'^[1/(r-1)];  x~ <- w / max(w)      next iterate (Alg. 1 divides by
 //                                            the l1 norm; TTSV1 and x^[r-1]
 //                                            are both homogeneous of degree
-//                                            r-1 so the ratio, the test and
+//                                            r-1, so the ratio, the test and
 //                                            the normalised x are unchanged)
-// The returned x is the iterate whose TTSV1 met the test, divided by its l1
-// norm (a fixed-shape, deterministic sum).
+// A finished graph is masked: its edges are skipped and its x is frozen.
+// The returned x of each graph is the iterate whose TTSV1 met the test,
+// divided by its l1 norm (fixed-shape, deterministic sum).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
-#include <limits>
+#include <vector>
 
 #include "internal.hpp"
 
 namespace sttsv {
 
-struct Ctrl {
-  int32_t done;
-  int32_t skip64;   // FP64-series edge kernels skip this iteration
-  int32_t skip32;   // FP32-series edge kernels skip this iteration
-  int32_t status;
+struct GCtrl {            // per graph
+  int32_t done, status;
   int32_t iter, it32, it64;
-  int32_t max_iter;
-  double tol, switch_tol, shift;
+  int32_t r;
   double lmin, lmax, crit, prev_crit;
   double inv_wmax;
 };
 
+struct SCtrl {            // per solve
+  int32_t all_done;
+  int32_t max_iter;
+  double tol, switch_tol, shift;
+};
+
 struct Solver {
-  int32_t n = 0;
+  int32_t n = 0, G = 0, nblk = 0;
   hipStream_t s = nullptr;
-  double* x = nullptr;      // current iterate, max-normalised
+  double* x = nullptr;        // current iterates, max-normalised per graph
   double* z = nullptr;
   double* w = nullptr;
-  double* part = nullptr;   // per-block partials
-  Ctrl* ctrl = nullptr;     // device
-  Ctrl* hctrl = nullptr;    // pinned host mirror
+  double* part = nullptr;     // per-block partials (4 per block)
+  double* sums = nullptr;     // per-graph l1 norms
+  int32_t* bgraph = nullptr;  // graph of each vertex block
+  int32_t* bsub = nullptr;    // block index inside its graph
+  int32_t* gblk0 = nullptr;   // first block of each graph
+  int32_t* gnblk = nullptr;   // blocks of each graph
+  int32_t* voff = nullptr;    // first vertex of each graph
+  int32_t* gn = nullptr;      // vertices of each graph
+  int32_t* skip64 = nullptr;  // graph skips the FP64-series edge launches
+  int32_t* skip32 = nullptr;  // graph skips the FP32-series edge launches
+  GCtrl* ctrl = nullptr;
+  SCtrl* sctrl = nullptr;
+  GCtrl* hctrl = nullptr;     // pinned host mirrors
+  SCtrl* hsctrl = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = 0;
   int graph_sched = -1;
@@ -54,88 +70,92 @@ struct Solver {
 namespace {
 
 constexpr int kRedBlock = 256;
-constexpr int kRedGrid = 1024;   // fixed: reduction shape depends on n only
+constexpr int kRedGrid = 1024;   // blocks per graph at most: shapes depend on n_g only
 
-int red_grid(int n) { return std::max(1, std::min(kRedGrid, (n + kRedBlock - 1) / kRedBlock)); }
+int blocks_of(int n) { return std::max(1, std::min(kRedGrid, (n + kRedBlock - 1) / kRedBlock)); }
 
-__device__ __forceinline__ double block_min(double v, double* sh) {
+template <typename F>
+__device__ __forceinline__ double block_reduce(double v, double* sh, F op) {
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = kRedBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + o]);
+    if (threadIdx.x < o) sh[threadIdx.x] = op(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
   const double r = sh[0];
   __syncthreads();
   return r;
 }
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
+struct OpMin {
+  __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMax {
+  __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct OpAdd {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+
+struct VBlock {         // vertex range of one block: v = v0 + tid + j*stride
+  int32_t g, v0, vend, stride;
+};
+
+__device__ __forceinline__ VBlock vblock(const Solver& S) {
+  VBlock b;
+  b.g = S.bgraph[blockIdx.x];
+  const int32_t sub = S.bsub[blockIdx.x];
+  b.v0 = S.voff[b.g] + sub * kRedBlock + threadIdx.x;
+  b.vend = S.voff[b.g] + S.gn[b.g];
+  b.stride = S.gnblk[b.g] * kRedBlock;
+  return b;
 }
 
-// Initial iterate: x~ = x0 / max(x0) (or all ones for the uniform start).
-// part[b] = {min x0, max x0, bad}
-__global__ void __launch_bounds__(kRedBlock) init_stats(const double* x0, int n, double* part) {
+// Initial iterate: x~ = x0 / max(x0) per graph.  part[b] = {max, bad}
+__global__ void __launch_bounds__(kRedBlock) init_stats(Solver S, const double* x0) {
   __shared__ double sh[kRedBlock];
-  double lo = INFINITY, hi = 0.0, bad = 0.0;
-  for (int v = blockIdx.x * kRedBlock + threadIdx.x; v < n; v += gridDim.x * kRedBlock) {
+  const VBlock vb = vblock(S);
+  double hi = 0.0, bad = 0.0;
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) {
     const double a = x0[v];
     if (!(a > 0.0) || !isfinite(a)) bad = 1.0;
-    lo = fmin(lo, a);
     hi = fmax(hi, a);
   }
-  lo = block_min(lo, sh);
-  hi = block_max(hi, sh);
-  bad = block_max(bad, sh);
+  hi = block_reduce(hi, sh, OpMax());
+  bad = block_reduce(bad, sh, OpMax());
   if (threadIdx.x == 0) {
-    part[3 * blockIdx.x] = lo;
-    part[3 * blockIdx.x + 1] = hi;
-    part[3 * blockIdx.x + 2] = bad;
+    S.part[4 * blockIdx.x] = hi;
+    S.part[4 * blockIdx.x + 1] = bad;
   }
 }
 
-__global__ void __launch_bounds__(kRedBlock) init_final(const double* part, int G, Ctrl* c) {
+__global__ void __launch_bounds__(kRedBlock) init_final(Solver S) {
   __shared__ double sh[kRedBlock];
+  const int g = blockIdx.x;
+  const int b0 = S.gblk0[g], nb = S.gnblk[g];
   double hi = 0.0, bad = 0.0;
-  for (int b = threadIdx.x; b < G; b += kRedBlock) {
-    hi = fmax(hi, part[3 * b + 1]);
-    bad = fmax(bad, part[3 * b + 2]);
+  for (int b = threadIdx.x; b < nb; b += kRedBlock) {
+    hi = fmax(hi, S.part[4 * (b0 + b)]);
+    bad = fmax(bad, S.part[4 * (b0 + b) + 1]);
   }
-  hi = block_max(hi, sh);
-  bad = block_max(bad, sh);
+  hi = block_reduce(hi, sh, OpMax());
+  bad = block_reduce(bad, sh, OpMax());
   if (threadIdx.x == 0) {
+    GCtrl& c = S.ctrl[g];
     if (bad > 0.0) {
-      c->done = 1;
-      c->skip64 = c->skip32 = 1;
-      c->status = STTSV_EINVAL;
+      c.done = 1;
+      c.status = STTSV_EINVAL;
+      S.skip64[g] = S.skip32[g] = 1;
     }
-    c->inv_wmax = 1.0 / hi;
+    c.inv_wmax = 1.0 / hi;
   }
 }
 
-__global__ void __launch_bounds__(kRedBlock) scale_into(const double* src, double* dst, int n, const Ctrl* c) {
-  if (c->done) return;
-  const int v = blockIdx.x * kRedBlock + threadIdx.x;
-  if (v < n) dst[v] = src[v] * c->inv_wmax;
+__global__ void __launch_bounds__(kRedBlock) scale_into(Solver S, const double* src, double* dst) {
+  const VBlock vb = vblock(S);
+  const GCtrl& c = S.ctrl[vb.g];
+  if (c.done) return;
+  const double f = c.inv_wmax;
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) dst[v] = src[v] * f;
 }
 
 __global__ void __launch_bounds__(kRedBlock) fill_ones(double* dst, int n) {
@@ -146,17 +166,19 @@ __global__ void __launch_bounds__(kRedBlock) fill_ones(double* dst, int n) {
 // Per-vertex step after TTSV1: shifted z, ratio lambda, next w.
 // part[b] = {min lambda, max lambda, max w, bad}
 template <bool LAMBDA>
-__global__ void __launch_bounds__(kRedBlock) nqz_stats(const double* x, const double* z, double* w, int n,
-                                                       int r, double* part, const Ctrl* c) {
-  if (c->done) return;
+__global__ void __launch_bounds__(kRedBlock) nqz_stats(Solver S) {
   __shared__ double sh[kRedBlock];
-  const double shift = c->shift;
+  const VBlock vb = vblock(S);
+  const GCtrl& c = S.ctrl[vb.g];
+  if (c.done) return;                               // uniform per block
+  const double shift = S.sctrl->shift;
+  const int r = c.r;
   const double inv = 1.0 / double(r - 1);
   double lo = INFINITY, hi = -INFINITY, wm = 0.0, bad = 0.0;
-  for (int v = blockIdx.x * kRedBlock + threadIdx.x; v < n; v += gridDim.x * kRedBlock) {
-    const double xv = x[v];
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) {
+    const double xv = S.x[v];
     const double p = pow(xv, double(r - 1));
-    const double zz = shift != 0.0 ? fma(shift, p, z[v]) : z[v];
+    const double zz = shift != 0.0 ? fma(shift, p, S.z[v]) : S.z[v];
     if (!(zz > 0.0) || !isfinite(zz)) bad = 1.0;
     if (LAMBDA) {
       const double lam = zz / p;
@@ -164,113 +186,125 @@ __global__ void __launch_bounds__(kRedBlock) nqz_stats(const double* x, const do
       hi = fmax(hi, lam);
     }
     const double wv = pow(zz, inv);
-    w[v] = wv;
+    S.w[v] = wv;
     wm = fmax(wm, wv);
   }
-  lo = block_min(lo, sh);
-  hi = block_max(hi, sh);
-  wm = block_max(wm, sh);
-  bad = block_max(bad, sh);
+  lo = block_reduce(lo, sh, OpMin());
+  hi = block_reduce(hi, sh, OpMax());
+  wm = block_reduce(wm, sh, OpMax());
+  bad = block_reduce(bad, sh, OpMax());
   if (threadIdx.x == 0) {
-    part[4 * blockIdx.x] = lo;
-    part[4 * blockIdx.x + 1] = hi;
-    part[4 * blockIdx.x + 2] = wm;
-    part[4 * blockIdx.x + 3] = bad;
+    S.part[4 * blockIdx.x] = lo;
+    S.part[4 * blockIdx.x + 1] = hi;
+    S.part[4 * blockIdx.x + 2] = wm;
+    S.part[4 * blockIdx.x + 3] = bad;
   }
 }
 
 template <bool LAMBDA>
-__global__ void __launch_bounds__(kRedBlock) nqz_final(const double* part, int G, Ctrl* c) {
-  if (c->done) return;
+__global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
   __shared__ double sh[kRedBlock];
+  const int g = blockIdx.x;
+  GCtrl& c = S.ctrl[g];
+  if (c.done) return;
+  const int b0 = S.gblk0[g], nb = S.gnblk[g];
   double lo = INFINITY, hi = -INFINITY, wm = 0.0, bad = 0.0;
-  for (int b = threadIdx.x; b < G; b += kRedBlock) {
-    lo = fmin(lo, part[4 * b]);
-    hi = fmax(hi, part[4 * b + 1]);
-    wm = fmax(wm, part[4 * b + 2]);
-    bad = fmax(bad, part[4 * b + 3]);
+  for (int b = threadIdx.x; b < nb; b += kRedBlock) {
+    lo = fmin(lo, S.part[4 * (b0 + b)]);
+    hi = fmax(hi, S.part[4 * (b0 + b) + 1]);
+    wm = fmax(wm, S.part[4 * (b0 + b) + 2]);
+    bad = fmax(bad, S.part[4 * (b0 + b) + 3]);
   }
-  lo = block_min(lo, sh);
-  hi = block_max(hi, sh);
-  wm = block_max(wm, sh);
-  bad = block_max(bad, sh);
+  lo = block_reduce(lo, sh, OpMin());
+  hi = block_reduce(hi, sh, OpMax());
+  wm = block_reduce(wm, sh, OpMax());
+  bad = block_reduce(bad, sh, OpMax());
   if (threadIdx.x != 0) return;
   if (bad > 0.0 || !(wm > 0.0) || !isfinite(wm)) {
-    c->done = 1;
-    c->skip64 = c->skip32 = 1;
-    c->status = STTSV_ENUMERIC;
+    c.done = 1;
+    c.status = STTSV_ENUMERIC;
+    S.skip64[g] = S.skip32[g] = 1;
     return;
   }
-  c->inv_wmax = 1.0 / wm;
+  c.inv_wmax = 1.0 / wm;
   if (!LAMBDA) return;
-  const bool ran64 = c->skip64 == 0;
+  const bool ran64 = S.skip64[g] == 0;
   const double crit = (hi - lo) / lo;
-  c->iter += 1;
+  c.iter += 1;
   if (ran64)
-    c->it64 += 1;
+    c.it64 += 1;
   else
-    c->it32 += 1;
-  c->lmin = lo;
-  c->lmax = hi;
-  c->crit = crit;
+    c.it32 += 1;
+  c.lmin = lo;
+  c.lmax = hi;
+  c.crit = crit;
   if (ran64) {
-    if (crit < c->tol) {
-      c->done = 1;
-      c->status = STTSV_OK;
+    if (crit < S.sctrl->tol) {
+      c.done = 1;
+      c.status = STTSV_OK;
     }
-  } else if (crit < c->switch_tol || crit < c->tol || crit > 0.8 * c->prev_crit) {
-    c->skip64 = 0;   // FP32 series have done what they can: polish in FP64
-    c->skip32 = 1;
+  } else if (crit < S.sctrl->switch_tol || crit < S.sctrl->tol || crit > 0.8 * c.prev_crit) {
+    S.skip64[g] = 0;   // FP32 series have done what they can: polish in FP64
+    S.skip32[g] = 1;
   }
-  c->prev_crit = crit;
-  if (!c->done && c->iter >= c->max_iter) {
-    c->done = 1;
-    c->status = STTSV_ENOTCONV;
+  c.prev_crit = crit;
+  if (!c.done && c.iter >= S.sctrl->max_iter) {
+    c.done = 1;
+    c.status = STTSV_ENOTCONV;
   }
-  if (c->done) c->skip64 = c->skip32 = 1;
+  if (c.done) S.skip64[g] = S.skip32[g] = 1;
 }
 
-__global__ void __launch_bounds__(kRedBlock) sum_stage(const double* x, int n, double* part) {
+// all_done = every graph done (single block)
+__global__ void __launch_bounds__(kRedBlock) all_done_check(Solver S) {
   __shared__ double sh[kRedBlock];
-  double acc = 0.0;
-  for (int v = blockIdx.x * kRedBlock + threadIdx.x; v < n; v += gridDim.x * kRedBlock) acc += x[v];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  double open = 0.0;
+  for (int g = threadIdx.x; g < S.G; g += kRedBlock) open = fmax(open, S.ctrl[g].done ? 0.0 : 1.0);
+  open = block_reduce(open, sh, OpMax());
+  if (threadIdx.x == 0) S.sctrl->all_done = open > 0.0 ? 0 : 1;
 }
 
-__global__ void __launch_bounds__(kRedBlock) sum_final(const double* part, int G, double* out) {
+__global__ void __launch_bounds__(kRedBlock) sum_stage(Solver S, const double* x) {
   __shared__ double sh[kRedBlock];
+  const VBlock vb = vblock(S);
   double acc = 0.0;
-  for (int b = threadIdx.x; b < G; b += kRedBlock) acc += part[b];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) *out = acc;
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) acc += x[v];
+  acc = block_reduce(acc, sh, OpAdd());
+  if (threadIdx.x == 0) S.part[4 * blockIdx.x] = acc;
 }
 
-__global__ void __launch_bounds__(kRedBlock) divide_by(const double* x, const double* s, double* out, int n) {
-  const int v = blockIdx.x * kRedBlock + threadIdx.x;
-  if (v < n) out[v] = x[v] / *s;
+__global__ void __launch_bounds__(kRedBlock) sum_final(Solver S) {
+  __shared__ double sh[kRedBlock];
+  const int g = blockIdx.x;
+  const int b0 = S.gblk0[g], nb = S.gnblk[g];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kRedBlock) acc += S.part[4 * (b0 + b)];
+  acc = block_reduce(acc, sh, OpAdd());
+  if (threadIdx.x == 0) S.sums[g] = acc;
 }
 
-int hip_rc(hipError_t e) { return e == hipSuccess ? STTSV_OK : STTSV_EHIP; }
+__global__ void __launch_bounds__(kRedBlock) divide_by(Solver S, const double* x, double* out) {
+  const VBlock vb = vblock(S);
+  const double s = S.sums[vb.g];
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) out[v] = x[v] / s;
+}
 
 // One NQZ iteration (all launches on S.s).
 hipError_t enqueue_iteration(Plan& p, Solver& S, int schedule) {
   hipError_t e;
-  const int G = red_grid(S.n);
-  if (schedule == STTSV_SOLVE_FP32_FP64) {
-    if ((e = launch_sttsv(p, S.x, S.z, STTSV_PREC_FP32, &S.ctrl->skip32, S.s)) != hipSuccess) return e;
-  }
-  // FP64 pass: its edge kernels and its reduction run only when skip64 == 0,
-  // those of the FP32 pass above only when skip32 == 0.
-  if ((e = launch_sttsv(p, S.x, S.z, STTSV_PREC_FP64, &S.ctrl->skip64, S.s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((nqz_stats<true>), dim3(G), dim3(kRedBlock), 0, S.s, S.x, S.z, S.w, S.n, p.r, S.part, S.ctrl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((nqz_final<true>), dim3(1), dim3(kRedBlock), 0, S.s, S.part, G, S.ctrl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(scale_into, dim3((S.n + kRedBlock - 1) / kRedBlock), dim3(kRedBlock), 0, S.s, S.w, S.x, S.n,
-                     S.ctrl);
+  const int32_t* all_done = &S.sctrl->all_done;
+  if (schedule == STTSV_SOLVE_FP32_FP64)
+    if ((e = launch_edges(p, S.x, STTSV_PREC_FP32, all_done, S.skip32, S.s)) != hipSuccess) return e;
+  if ((e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s)) != hipSuccess) return e;
+  if ((e = launch_reduction(p, S.z, all_done, S.s)) != hipSuccess) return e;
+  hipLaunchKernelGGL((nqz_stats<true>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL((nqz_final<true>), dim3(S.G), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
   return hipGetLastError();
 }
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? STTSV_OK : STTSV_EHIP; }
 
 }  // namespace
 
@@ -278,12 +312,12 @@ void free_solver(Plan& p) {
   Solver* S = p.solver;
   if (S == nullptr) return;
   if (S->exec) (void)hipGraphExecDestroy(S->exec);
-  (void)hipFree(S->x);
-  (void)hipFree(S->z);
-  (void)hipFree(S->w);
-  (void)hipFree(S->part);
-  (void)hipFree(S->ctrl);
+  for (void* q : {(void*)S->x, (void*)S->z, (void*)S->w, (void*)S->part, (void*)S->sums, (void*)S->bgraph,
+                  (void*)S->bsub, (void*)S->gblk0, (void*)S->gnblk, (void*)S->voff, (void*)S->gn,
+                  (void*)S->skip64, (void*)S->skip32, (void*)S->ctrl, (void*)S->sctrl})
+    (void)hipFree(q);
   if (S->hctrl) (void)hipHostFree(S->hctrl);
+  if (S->hsctrl) (void)hipHostFree(S->hsctrl);
   if (S->s) (void)hipStreamDestroy(S->s);
   delete S;
   p.solver = nullptr;
@@ -293,88 +327,123 @@ static int ensure_solver(Plan& p) {
   if (p.solver != nullptr) return STTSV_OK;
   Solver* S = new Solver();
   p.solver = S;
+  const int G = static_cast<int>(p.graphs.size());
   S->n = p.n;
+  S->G = G;
+  std::vector<int32_t> bgraph, bsub, gblk0(G), gnblk(G), voff(G), gn(G);
+  for (int g = 0; g < G; ++g) {
+    gblk0[g] = static_cast<int32_t>(bgraph.size());
+    gnblk[g] = blocks_of(p.graphs[g].n);
+    voff[g] = p.graphs[g].voff;
+    gn[g] = p.graphs[g].n;
+    for (int b = 0; b < gnblk[g]; ++b) {
+      bgraph.push_back(g);
+      bsub.push_back(b);
+    }
+  }
+  S->nblk = static_cast<int32_t>(bgraph.size());
   const size_t nb = size_t(p.n) * sizeof(double);
   if (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) return STTSV_EHIP;
-  if (hipMalloc(&S->x, nb) != hipSuccess || hipMalloc(&S->z, nb) != hipSuccess ||
-      hipMalloc(&S->w, nb) != hipSuccess || hipMalloc(&S->part, 4 * kRedGrid * sizeof(double)) != hipSuccess ||
-      hipMalloc(&S->ctrl, sizeof(Ctrl)) != hipSuccess)
+  auto alloc = [](auto** ptr, size_t bytes) { return hipMalloc(reinterpret_cast<void**>(ptr), bytes) == hipSuccess; };
+  if (!alloc(&S->x, nb) || !alloc(&S->z, nb) || !alloc(&S->w, nb) ||
+      !alloc(&S->part, 4 * sizeof(double) * S->nblk) || !alloc(&S->sums, sizeof(double) * G) ||
+      !alloc(&S->bgraph, 4 * S->nblk) || !alloc(&S->bsub, 4 * S->nblk) || !alloc(&S->gblk0, 4 * G) ||
+      !alloc(&S->gnblk, 4 * G) || !alloc(&S->voff, 4 * G) || !alloc(&S->gn, 4 * G) ||
+      !alloc(&S->skip64, 4 * G) || !alloc(&S->skip32, 4 * G) || !alloc(&S->ctrl, sizeof(GCtrl) * G) ||
+      !alloc(&S->sctrl, sizeof(SCtrl)))
     return STTSV_ENOMEM;
-  if (hipHostMalloc(&S->hctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) return STTSV_ENOMEM;
+  if (hipHostMalloc(&S->hctrl, sizeof(GCtrl) * G, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&S->hsctrl, sizeof(SCtrl), hipHostMallocDefault) != hipSuccess)
+    return STTSV_ENOMEM;
+  auto up = [](void* d, const void* h, size_t bytes) { return hipMemcpy(d, h, bytes, hipMemcpyHostToDevice) == hipSuccess; };
+  if (!up(S->bgraph, bgraph.data(), 4 * bgraph.size()) || !up(S->bsub, bsub.data(), 4 * bsub.size()) ||
+      !up(S->gblk0, gblk0.data(), 4 * G) || !up(S->gnblk, gnblk.data(), 4 * G) || !up(S->voff, voff.data(), 4 * G) ||
+      !up(S->gn, gn.data(), 4 * G))
+    return STTSV_EHIP;
   return STTSV_OK;
 }
 
 int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, double* x_out,
-          sttsv_solve_info* info) {
+          sttsv_solve_info* infos) {
   if (!(tol > 0.0) || x_out == nullptr) return STTSV_EINVAL;
-  if (o.max_iter < 1 || o.check_every < 1 || o.shift < 0.0) return STTSV_EINVAL;
+  if (o.max_iter < 1 || o.check_every < 1 || !(o.shift >= 0.0)) return STTSV_EINVAL;
   if (o.schedule != STTSV_SOLVE_FP64 && o.schedule != STTSV_SOLVE_FP32_FP64) return STTSV_EINVAL;
   if (!p.connected) return STTSV_EDISCONNECTED;
   int rc = ensure_solver(p);
   if (rc != STTSV_OK) return rc;
   Solver& S = *p.solver;
+  const int G = S.G;
   const int n = p.n;
-  const int G = red_grid(n);
-  const dim3 gv((n + kRedBlock - 1) / kRedBlock);
   if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
 
-  // control block
-  Ctrl c{};
-  c.done = 0;
-  c.skip64 = o.schedule == STTSV_SOLVE_FP32_FP64 ? 1 : 0;
-  c.skip32 = o.schedule == STTSV_SOLVE_FP32_FP64 ? 0 : 1;
-  c.status = STTSV_OK;
-  c.max_iter = o.max_iter;
-  c.tol = tol;
-  c.switch_tol = o.switch_tol;
-  c.shift = o.shift;
-  c.prev_crit = INFINITY;
-  c.crit = INFINITY;
-  if (hipMemcpyAsync(S.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, S.s) != hipSuccess) return STTSV_EHIP;
+  // control blocks
+  std::vector<GCtrl> c(G);
+  std::vector<int32_t> s64(G), s32(G);
+  for (int g = 0; g < G; ++g) {
+    c[g] = GCtrl{};
+    c[g].status = STTSV_OK;
+    c[g].r = p.graphs[g].r;
+    c[g].prev_crit = INFINITY;
+    c[g].crit = INFINITY;
+    s64[g] = o.schedule == STTSV_SOLVE_FP32_FP64 ? 1 : 0;
+    s32[g] = o.schedule == STTSV_SOLVE_FP32_FP64 ? 0 : 1;
+  }
+  SCtrl sc{};
+  sc.all_done = 0;
+  sc.max_iter = o.max_iter;
+  sc.tol = tol;
+  sc.switch_tol = o.switch_tol;
+  sc.shift = o.shift;
+  if (hipMemcpyAsync(S.ctrl, c.data(), sizeof(GCtrl) * G, hipMemcpyHostToDevice, S.s) != hipSuccess ||
+      hipMemcpyAsync(S.sctrl, &sc, sizeof(SCtrl), hipMemcpyHostToDevice, S.s) != hipSuccess ||
+      hipMemcpyAsync(S.skip64, s64.data(), 4 * G, hipMemcpyHostToDevice, S.s) != hipSuccess ||
+      hipMemcpyAsync(S.skip32, s32.data(), 4 * G, hipMemcpyHostToDevice, S.s) != hipSuccess)
+    return STTSV_EHIP;
 
   // initial iterate (Alg. 1: y = 1/n, or the warm start), then z = TTSV1(y)
-  // and the first x; scale of y is irrelevant (homogeneity), so y / max(y).
+  // and the first x; the scale of y is irrelevant (homogeneity), so y / max(y)
   if (x0 == nullptr) {
-    hipLaunchKernelGGL(fill_ones, gv, dim3(kRedBlock), 0, S.s, S.x, n);
+    hipLaunchKernelGGL(fill_ones, dim3((n + kRedBlock - 1) / kRedBlock), dim3(kRedBlock), 0, S.s, S.x, n);
   } else {
-    hipLaunchKernelGGL(init_stats, dim3(G), dim3(kRedBlock), 0, S.s, x0, n, S.part);
-    hipLaunchKernelGGL(init_final, dim3(1), dim3(kRedBlock), 0, S.s, S.part, G, S.ctrl);
-    hipLaunchKernelGGL(scale_into, gv, dim3(kRedBlock), 0, S.s, x0, S.x, n, S.ctrl);
+    hipLaunchKernelGGL(init_stats, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, x0);
+    hipLaunchKernelGGL(init_final, dim3(G), dim3(kRedBlock), 0, S.s, S);
+    hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, x0, S.x);
   }
   const int first_prec = o.schedule == STTSV_SOLVE_FP32_FP64 ? STTSV_PREC_FP32 : STTSV_PREC_FP64;
-  if ((rc = hip_rc(launch_sttsv(p, S.x, S.z, first_prec, &S.ctrl->done, S.s))) != STTSV_OK) return rc;
-  hipLaunchKernelGGL((nqz_stats<false>), dim3(G), dim3(kRedBlock), 0, S.s, S.x, S.z, S.w, n, p.r, S.part, S.ctrl);
-  hipLaunchKernelGGL((nqz_final<false>), dim3(1), dim3(kRedBlock), 0, S.s, S.part, G, S.ctrl);
-  hipLaunchKernelGGL(scale_into, gv, dim3(kRedBlock), 0, S.s, S.w, S.x, n, S.ctrl);
+  const int32_t* first_skip = first_prec == STTSV_PREC_FP32 ? S.skip32 : S.skip64;
+  if ((rc = hip_rc(launch_edges(p, S.x, first_prec, nullptr, first_skip, S.s))) != STTSV_OK) return rc;
+  if ((rc = hip_rc(launch_reduction(p, S.z, nullptr, S.s))) != STTSV_OK) return rc;
+  hipLaunchKernelGGL((nqz_stats<false>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL((nqz_final<false>), dim3(G), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
   if (hipGetLastError() != hipSuccess) return STTSV_EHIP;
 
   // iterations: captured graph of check_every iterations, or direct launches
   const int K = o.check_every;
-  if (o.use_graph) {
-    if (S.exec == nullptr || S.graph_iters != K || S.graph_sched != o.schedule) {
-      if (S.exec) {
-        (void)hipGraphExecDestroy(S.exec);
-        S.exec = nullptr;
-      }
-      if (hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
-      hipGraph_t g = nullptr;
-      if (hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal) != hipSuccess) return STTSV_EHIP;
-      hipError_t e = hipSuccess;
-      for (int t = 0; t < K && e == hipSuccess; ++t) e = enqueue_iteration(p, S, o.schedule);
-      hipError_t e2 = hipStreamEndCapture(S.s, &g);
-      if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return STTSV_EHIP;
-      }
-      e = hipGraphInstantiate(&S.exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        S.exec = nullptr;
-        return STTSV_EHIP;
-      }
-      S.graph_iters = K;
-      S.graph_sched = o.schedule;
+  if (o.use_graph && (S.exec == nullptr || S.graph_iters != K || S.graph_sched != o.schedule)) {
+    if (S.exec) {
+      (void)hipGraphExecDestroy(S.exec);
+      S.exec = nullptr;
     }
+    if (hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal) != hipSuccess) return STTSV_EHIP;
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < K && e == hipSuccess; ++t) e = enqueue_iteration(p, S, o.schedule);
+    const hipError_t e2 = hipStreamEndCapture(S.s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return STTSV_EHIP;
+    }
+    e = hipGraphInstantiate(&S.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      S.exec = nullptr;
+      return STTSV_EHIP;
+    }
+    S.graph_iters = K;
+    S.graph_sched = o.schedule;
   }
   for (;;) {
     if (o.use_graph) {
@@ -383,30 +452,37 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
       for (int t = 0; t < K; ++t)
         if (enqueue_iteration(p, S, o.schedule) != hipSuccess) return STTSV_EHIP;
     }
-    if (hipMemcpyAsync(S.hctrl, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, S.s) != hipSuccess) return STTSV_EHIP;
+    if (hipMemcpyAsync(S.hsctrl, S.sctrl, sizeof(SCtrl), hipMemcpyDeviceToHost, S.s) != hipSuccess) return STTSV_EHIP;
     if (hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
-    if (S.hctrl->done) break;
+    if (S.hsctrl->all_done) break;
   }
-  const Ctrl& h = *S.hctrl;
-  if (h.status == STTSV_EINVAL) return STTSV_EINVAL;   // warm start not > 0 / finite
+  if (hipMemcpy(S.hctrl, S.ctrl, sizeof(GCtrl) * G, hipMemcpyDeviceToHost) != hipSuccess) return STTSV_EHIP;
 
-  // x_out = x~ / ||x~||_1
-  double* dsum = S.part + 4 * kRedGrid - 1;
-  hipLaunchKernelGGL(sum_stage, dim3(G), dim3(kRedBlock), 0, S.s, S.x, n, S.part);
-  hipLaunchKernelGGL(sum_final, dim3(1), dim3(kRedBlock), 0, S.s, S.part, G, dsum);
-  hipLaunchKernelGGL(divide_by, gv, dim3(kRedBlock), 0, S.s, S.x, dsum, x_out, n);
+  // x_out = x~ / ||x~||_1 per graph
+  hipLaunchKernelGGL(sum_stage, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.x);
+  hipLaunchKernelGGL(sum_final, dim3(G), dim3(kRedBlock), 0, S.s, S);
+  hipLaunchKernelGGL(divide_by, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.x, x_out);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
 
-  if (info != nullptr) {
-    info->iterations = h.iter;
-    info->iters_fp32 = h.it32;
-    info->iters_fp64 = h.it64;
-    info->converged = h.status == STTSV_OK && h.iter > 0 ? 1 : 0;
-    info->lambda_min = h.lmin - o.shift;
-    info->lambda_max = h.lmax - o.shift;
-    info->criterion = h.crit;
+  // overall status: the worst of the graphs' (EINVAL > ENUMERIC > ENOTCONV > OK)
+  int worst = STTSV_OK;
+  auto severity = [](int st) {
+    return st == STTSV_EINVAL ? 3 : st == STTSV_ENUMERIC ? 2 : st == STTSV_ENOTCONV ? 1 : 0;
+  };
+  for (int g = 0; g < G; ++g) {
+    const GCtrl& h = S.hctrl[g];
+    if (severity(h.status) > severity(worst)) worst = h.status;
+    if (infos != nullptr) {
+      infos[g].iterations = h.iter;
+      infos[g].iters_fp32 = h.it32;
+      infos[g].iters_fp64 = h.it64;
+      infos[g].converged = h.status == STTSV_OK && h.iter > 0 ? 1 : 0;
+      infos[g].lambda_min = h.lmin - o.shift;
+      infos[g].lambda_max = h.lmax - o.shift;
+      infos[g].criterion = h.crit;
+    }
   }
-  return h.status;
+  return worst;
 }
 
 }  // namespace sttsv

@@ -111,6 +111,7 @@ void free_plan(Plan* p) {
   free_solver(*p);
   (void)hipFree(p->d_mem);
   (void)hipFree(p->d_pos);
+  (void)hipFree(p->d_gid);
   (void)hipFree(p->d_contrib);
   for (auto& g : p->groups) {
     (void)hipFree(g.d_bks);
@@ -129,81 +130,66 @@ void free_plan(Plan* p) {
   delete p;
 }
 
-int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, int32_t r,
-               const sttsv_opts* opts, Plan** out) {
-  if (eptr == nullptr || eidx == nullptr || out == nullptr) return STTSV_EINVAL;
-  if (m < 1 || n < 1) return STTSV_EINVAL;
-  if (r < 2 || r > STTSV_MAX_ORDER) return STTSV_ENOTSUP;
-  if (opts != nullptr && opts->precision != STTSV_PREC_FP64 && opts->precision != STTSV_PREC_FP32)
-    return STTSV_EINVAL;
-  if (eptr[0] != 0) return STTSV_EINVAL;
-  for (int64_t e = 0; e < m; ++e) {
-    const int64_t k = eptr[e + 1] - eptr[e];
-    if (k < 1 || k > r) return STTSV_EINVAL;
-  }
-  const int64_t nnz = eptr[m];
-  if (nnz > INT32_MAX) return STTSV_ENOTSUP;
+namespace {
 
-  // ---- validation of members, degrees
-  std::vector<int64_t> deg(n, 0);
-  {
-    std::vector<int64_t> seen(n, -1);
-    for (int64_t e = 0; e < m; ++e) {
-      for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) {
-        const int32_t v = eidx[p];
-        if (v < 0 || v >= n) return STTSV_EINVAL;
-        if (seen[v] == e) return STTSV_EINVAL;   // repeated vertex in an edge
-        seen[v] = e;
-        deg[v]++;
-      }
+// Checks of one hypergraph (problem statement of Sec. II: a set system of
+// non-empty vertex subsets of size <= r).  Fills deg on success.
+int validate_graph(const GraphIn& g, std::vector<int64_t>& deg) {
+  if (g.eptr == nullptr || g.eidx == nullptr) return STTSV_EINVAL;
+  if (g.m < 1 || g.n < 1) return STTSV_EINVAL;
+  if (g.r < 2 || g.r > STTSV_MAX_ORDER) return STTSV_ENOTSUP;
+  if (g.eptr[0] != 0) return STTSV_EINVAL;
+  for (int64_t e = 0; e < g.m; ++e) {
+    const int64_t k = g.eptr[e + 1] - g.eptr[e];
+    if (k < 1 || k > g.r) return STTSV_EINVAL;
+  }
+  deg.assign(g.n, 0);
+  std::vector<int64_t> seen(g.n, -1);
+  for (int64_t e = 0; e < g.m; ++e) {
+    for (int64_t p = g.eptr[e]; p < g.eptr[e + 1]; ++p) {
+      const int32_t v = g.eidx[p];
+      if (v < 0 || v >= g.n) return STTSV_EINVAL;
+      if (seen[v] == e) return STTSV_EINVAL;   // repeated vertex in an edge
+      seen[v] = e;
+      deg[v]++;
     }
   }
+  return STTSV_OK;
+}
 
-  Plan* P = new Plan();
-  P->m = m;
-  P->nnz = nnz;
-  P->n = n;
-  P->r = r;
-  P->precision = opts ? opts->precision : STTSV_PREC_FP64;
-  P->flags = opts ? opts->flags : 0;
-  P->stream = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
-  (void)hipGetDevice(&P->device);
+// Canonical order of one graph: vertex ranks (degree descending, id
+// ascending), members of every edge by rank, and for every size k the edges
+// sorted by (member-rank sequence, input index).  rk holds each edge's
+// member ranks, sorted, at the edge's CSR offsets.
+struct Canon {
+  std::vector<int32_t> inv_rank;                 // rank -> vertex
+  std::vector<int32_t> rk;
+  std::vector<std::vector<int64_t>> order;       // [k] -> input edges, canonical
+};
 
-  // ---- vertex rank: degree descending, id ascending (counting sort by degree)
+void canonicalise(const GraphIn& g, const std::vector<int64_t>& deg, Canon& c) {
+  const int32_t n = g.n;
   std::vector<int32_t> rank(n);
-  {
-    int64_t maxd = 0;
-    for (int64_t d : deg) maxd = std::max(maxd, d);
-    std::vector<int64_t> cnt(maxd + 2, 0);
-    for (int64_t d : deg) cnt[maxd - d + 1]++;
-    for (int64_t i = 1; i < (int64_t)cnt.size(); ++i) cnt[i] += cnt[i - 1];
-    for (int32_t v = 0; v < n; ++v) rank[v] = static_cast<int32_t>(cnt[maxd - deg[v]]++);
-  }
-
-  // ---- per-edge member ranks, sorted within the edge
-  std::vector<int32_t> rk(nnz);
-  for (int64_t e = 0; e < m; ++e) {
-    int32_t* a = rk.data() + eptr[e];
-    const int64_t k = eptr[e + 1] - eptr[e];
-    for (int64_t j = 0; j < k; ++j) a[j] = rank[eidx[eptr[e] + j]];
+  int64_t maxd = 0;
+  for (int64_t d : deg) maxd = std::max(maxd, d);
+  std::vector<int64_t> cnt(maxd + 2, 0);
+  for (int64_t d : deg) cnt[maxd - d + 1]++;
+  for (int64_t i = 1; i < (int64_t)cnt.size(); ++i) cnt[i] += cnt[i - 1];
+  for (int32_t v = 0; v < n; ++v) rank[v] = static_cast<int32_t>(cnt[maxd - deg[v]]++);
+  c.inv_rank.assign(n, 0);
+  for (int32_t v = 0; v < n; ++v) c.inv_rank[rank[v]] = v;
+  const int64_t nnz = g.eptr[g.m];
+  c.rk.assign(nnz, 0);
+  for (int64_t e = 0; e < g.m; ++e) {
+    int32_t* a = c.rk.data() + g.eptr[e];
+    const int64_t k = g.eptr[e + 1] - g.eptr[e];
+    for (int64_t j = 0; j < k; ++j) a[j] = rank[g.eidx[g.eptr[e] + j]];
     std::sort(a, a + k);
   }
-
-  // ---- buckets by size, canonical order inside each
-  std::vector<int64_t> mk(r + 1, 0);
-  for (int64_t e = 0; e < m; ++e) mk[eptr[e + 1] - eptr[e]]++;
-  std::vector<std::vector<int64_t>> members_of(r + 1);
-  for (int k = 1; k <= r; ++k) members_of[k].reserve(mk[k]);
-  for (int64_t e = 0; e < m; ++e) members_of[eptr[e + 1] - eptr[e]].push_back(e);
-
-  std::vector<int32_t> inv_rank(n);
-  for (int32_t v = 0; v < n; ++v) inv_rank[rank[v]] = v;
-
-  P->perm.resize(m);
-  P->mem.resize(nnz);
-  int64_t edge_off = 0, slot_off = 0;
-  for (int k = 1; k <= r; ++k) {
-    auto& ids = members_of[k];
+  c.order.assign(g.r + 1, {});
+  for (int64_t e = 0; e < g.m; ++e) c.order[g.eptr[e + 1] - g.eptr[e]].push_back(e);
+  for (int k = 1; k <= g.r; ++k) {
+    auto& ids = c.order[k];
     if (ids.empty()) continue;
     struct Key {
       uint64_t head;
@@ -211,63 +197,159 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
     };
     std::vector<Key> keys(ids.size());
     for (size_t t = 0; t < ids.size(); ++t) {
-      const int32_t* a = rk.data() + eptr[ids[t]];
+      const int32_t* a = c.rk.data() + g.eptr[ids[t]];
       const uint64_t r0 = (uint64_t)(uint32_t)a[0];
       const uint64_t r1 = k > 1 ? (uint64_t)(uint32_t)a[1] : 0;
       keys[t] = Key{(r0 << 32) | r1, ids[t]};
     }
     std::sort(keys.begin(), keys.end(), [&](const Key& x, const Key& y) {
       if (x.head != y.head) return x.head < y.head;
-      const int32_t* a = rk.data() + eptr[x.id];
-      const int32_t* b = rk.data() + eptr[y.id];
+      const int32_t* a = c.rk.data() + g.eptr[x.id];
+      const int32_t* b = c.rk.data() + g.eptr[y.id];
       for (int j = 2; j < k; ++j)
         if (a[j] != b[j]) return a[j] < b[j];
       return x.id < y.id;
     });
-    Bucket B;
-    B.k = k;
-    B.m = (int64_t)ids.size();
-    B.edge_off = edge_off;
-    B.slot_off = slot_off;
-    for (int64_t i = 0; i < B.m; ++i) {
-      const int64_t e = keys[i].id;
-      P->perm[edge_off + i] = e;
-      const int32_t* a = rk.data() + eptr[e];
-      for (int j = 0; j < k; ++j) P->mem[slot_off + j * B.m + i] = inv_rank[a[j]];
-    }
-    if (k > 1) B.fp32_ok = fp32_scale(r, k, &B.qexp32);
-    P->buckets.push_back(B);
-    edge_off += B.m;
-    slot_off += (int64_t)k * B.m;
+    for (size_t t = 0; t < ids.size(); ++t) ids[t] = keys[t].id;
   }
-  rk.clear();
-  rk.shrink_to_fit();
+}
 
-  // ---- node-major incidence lists in canonical edge order
-  P->tptr.assign(n + 1, 0);
-  for (int32_t v = 0; v < n; ++v) P->tptr[v + 1] = P->tptr[v] + deg[v];
-  P->tslot.resize(nnz);
+bool connected_graph(const GraphIn& g, const std::vector<int64_t>& deg) {
+  Dsu d(g.n);
+  for (int64_t e = 0; e < g.m; ++e)
+    for (int64_t p = g.eptr[e] + 1; p < g.eptr[e + 1]; ++p) d.unite(g.eidx[g.eptr[e]], g.eidx[p]);
+  for (int32_t v = 0; v < g.n; ++v)
+    if (deg[v] == 0 || d.find(v) != 0) return false;
+  return true;
+}
+
+}  // namespace
+
+int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
+  if (G < 1 || gs == nullptr || out == nullptr) return STTSV_EINVAL;
+  if (opts != nullptr && opts->precision != STTSV_PREC_FP64 && opts->precision != STTSV_PREC_FP32)
+    return STTSV_EINVAL;
+  // ---- validation, sizes
+  std::vector<std::vector<int64_t>> degs(G);
+  int64_t m = 0, nnz = 0, n64 = 0;
+  int32_t rmax = 0;
+  for (int g = 0; g < G; ++g) {
+    const int rc = validate_graph(gs[g], degs[g]);
+    if (rc != STTSV_OK) return rc;
+    m += gs[g].m;
+    nnz += gs[g].eptr[gs[g].m];
+    n64 += gs[g].n;
+    rmax = std::max(rmax, gs[g].r);
+  }
+  if (nnz > INT32_MAX || n64 > INT32_MAX || m > INT32_MAX) return STTSV_ENOTSUP;
+  const int32_t n = static_cast<int32_t>(n64);
+
+  Plan* P = new Plan();
+  P->m = m;
+  P->nnz = nnz;
+  P->n = n;
+  P->r = rmax;
+  P->precision = opts ? opts->precision : STTSV_PREC_FP64;
+  P->flags = opts ? opts->flags : 0;
+  P->stream = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+  (void)hipGetDevice(&P->device);
+  P->graphs.resize(G);
+  {
+    int32_t voff = 0;
+    int64_t eoff = 0;
+    for (int g = 0; g < G; ++g) {
+      GraphInfo& I = P->graphs[g];
+      I.m = gs[g].m;
+      I.nnz = gs[g].eptr[gs[g].m];
+      I.n = gs[g].n;
+      I.r = gs[g].r;
+      I.voff = voff;
+      I.eoff = eoff;
+      voff += gs[g].n;
+      eoff += gs[g].m;
+    }
+  }
+
+  // ---- buckets keyed by (r, k); every graph's edges of size k form a
+  // contiguous run of its bucket, in the graph's own canonical order
+  std::vector<std::vector<int64_t>> cnt_rk(rmax + 1, std::vector<int64_t>(rmax + 1, 0));
+  std::vector<std::vector<int64_t>> goff(G, std::vector<int64_t>(rmax + 1, 0));
+  for (int g = 0; g < G; ++g) {
+    std::vector<int64_t> mk(gs[g].r + 1, 0);
+    for (int64_t e = 0; e < gs[g].m; ++e) mk[gs[g].eptr[e + 1] - gs[g].eptr[e]]++;
+    for (int k = 1; k <= gs[g].r; ++k) {
+      goff[g][k] = cnt_rk[gs[g].r][k];
+      cnt_rk[gs[g].r][k] += mk[k];
+    }
+  }
+  std::vector<std::vector<int>> bidx(rmax + 1, std::vector<int>(rmax + 1, -1));
+  {
+    int64_t edge_off = 0, slot_off = 0;
+    for (int r = 2; r <= rmax; ++r)
+      for (int k = 1; k <= r; ++k) {
+        if (cnt_rk[r][k] == 0) continue;
+        Bucket B;
+        B.r = r;
+        B.k = k;
+        B.m = cnt_rk[r][k];
+        B.edge_off = edge_off;
+        B.slot_off = slot_off;
+        if (k > 1) B.fp32_ok = fp32_scale(r, k, &B.qexp32);
+        bidx[r][k] = static_cast<int>(P->buckets.size());
+        P->buckets.push_back(B);
+        edge_off += B.m;
+        slot_off += (int64_t)k * B.m;
+      }
+  }
+
+  // ---- member slots, canonical permutation, graph ids, node-major lists
+  P->perm.assign(m, 0);
+  P->mem.assign(nnz, 0);
+  P->tptr.assign((size_t)n + 1, 0);
+  for (int g = 0; g < G; ++g)
+    for (int32_t v = 0; v < gs[g].n; ++v) {
+      const int64_t u = (int64_t)P->graphs[g].voff + v;
+      P->tptr[u + 1] = P->tptr[u] + degs[g][v];
+    }
+  P->tslot.assign(nnz, 0);
+  std::vector<int32_t> gid;
+  if (G > 1) gid.assign(m, 0);
   {
     std::vector<int64_t> cur(P->tptr.begin(), P->tptr.end() - 1);
-    for (const Bucket& B : P->buckets)
-      for (int64_t i = 0; i < B.m; ++i)
-        for (int j = 0; j < B.k; ++j) {
-          const int64_t s = B.slot_off + j * B.m + i;
-          P->tslot[cur[P->mem[s]]++] = static_cast<int32_t>(s);
+    for (int g = 0; g < G; ++g) {
+      const GraphIn& in = gs[g];
+      const GraphInfo& I = P->graphs[g];
+      Canon c;
+      canonicalise(in, degs[g], c);
+      for (int k = 1; k <= in.r; ++k) {
+        const auto& ids = c.order[k];
+        if (ids.empty()) continue;
+        const Bucket& B = P->buckets[bidx[in.r][k]];
+        const int64_t base = goff[g][k];
+        for (size_t t = 0; t < ids.size(); ++t) {
+          const int64_t e = ids[t];
+          const int64_t i = base + (int64_t)t;                  // edge index in the bucket
+          P->perm[B.edge_off + i] = I.eoff + e;
+          if (G > 1) gid[B.edge_off + i] = g;
+          const int32_t* a = c.rk.data() + in.eptr[e];
+          for (int j = 0; j < k; ++j) {
+            const int32_t u = I.voff + c.inv_rank[a[j]];
+            const int64_t s = B.slot_off + (int64_t)j * B.m + i;
+            P->mem[s] = u;
+            P->tslot[cur[u]++] = static_cast<int32_t>(s);
+          }
         }
+      }
+      P->graphs[g].connected = connected_graph(in, degs[g]);
+    }
   }
-
-  // ---- connectivity (Perron-Frobenius condition for the solver)
-  {
-    Dsu d(n);
-    for (int64_t e = 0; e < m; ++e)
-      for (int64_t p = eptr[e] + 1; p < eptr[e + 1]; ++p) d.unite(eidx[eptr[e]], eidx[p]);
-    bool ok = true;
-    for (int32_t v = 0; v < n && ok; ++v) ok = deg[v] > 0 && d.find(v) == 0;
-    P->connected = ok;
-  }
-
-  P->weights = weight_table(r);
+  P->connected = true;
+  for (const GraphInfo& I : P->graphs) P->connected = P->connected && I.connected;
+  P->weights = weight_table(gs[0].r);
+  std::vector<int64_t> deg(n);
+  for (int g = 0; g < G; ++g)
+    for (int32_t v = 0; v < gs[g].n; ++v) deg[(int64_t)P->graphs[g].voff + v] = degs[g][v];
+  degs.clear();
 
   // ---- reduction schedule
   struct HostLevel {
@@ -351,6 +433,7 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
     if ((rc = upload(&P->d_pos, pos.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   }
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
   for (size_t l = 0; l < hl.size(); ++l) {
     ReduceLevel L;
     L.nchunks = (int64_t)hl[l].len.size();
@@ -368,12 +451,16 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
   }
   // ---- kernel selection, bucket descriptors, fused generic groups
   const EdgeTables& tab = edge_tables();
+  std::vector<std::vector<double>> wtab(rmax + 1);
   for (Bucket& B : P->buckets) {
+    const int r = B.r;
     const int W = r - B.k + 1;
+    if (wtab[r].empty()) wtab[r] = weight_table(r);
     for (int t = 0; t < 2; ++t) {
       BucketDesc& d = B.desc[t];
       d.mem = P->d_mem + B.slot_off;
       d.pos = P->d_pos + B.slot_off;
+      d.gid = P->d_gid != nullptr ? P->d_gid + B.edge_off : nullptr;
       d.gstack = nullptr;
       d.m = B.m;
       d.k = B.k;
@@ -382,7 +469,7 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
       d.qexp = t == 1 ? B.qexp32 : 0;
       d.lds_stack = 1;
       d.pad = 0;
-      d.wk = P->weights[B.k];
+      d.wk = wtab[r][B.k];
       const auto& small = t == 0 ? tab.small64 : tab.small32;
       int kind = -1;
       if (B.k == 2) kind = SK_K2;
@@ -395,37 +482,37 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
   for (int seq = 0; seq < 2; ++seq) {
     for (int rg = 0; rg < kGenRanges; ++rg) {
       for (int t = 0; t < 2; ++t) {
-        GenGroup G;
-        G.range = rg;
-        G.seq = seq;
-        G.f64 = t == 0;
+        GenGroup grp;
+        grp.range = rg;
+        grp.seq = seq;
+        grp.f64 = t == 0;
         for (size_t b = 0; b < P->buckets.size(); ++b) {
           const Bucket& B = P->buckets[b];
           const int type = (seq == 0 || !B.fp32_ok || B.k == 1) ? 0 : 1;
           if (type != t || B.k < 4 || B.small_kind[t] >= 0) continue;
-          if (gen_range_of(r - B.k + 1) != rg) continue;
-          G.buckets.push_back(static_cast<int>(b));
+          if (gen_range_of(B.r - B.k + 1) != rg) continue;
+          grp.buckets.push_back(static_cast<int>(b));
         }
-        if (G.buckets.empty()) continue;
+        if (grp.buckets.empty()) continue;
         // longest per-edge work first, so the slow blocks start early
-        std::stable_sort(G.buckets.begin(), G.buckets.end(), [&](int a, int b) {
+        std::stable_sort(grp.buckets.begin(), grp.buckets.end(), [&](int a, int b) {
           const Bucket& A = P->buckets[a];
           const Bucket& B = P->buckets[b];
-          const int64_t wa = (int64_t)(A.k - 3) * (r - A.k + 1) * (r - A.k + 1);
-          const int64_t wb = (int64_t)(B.k - 3) * (r - B.k + 1) * (r - B.k + 1);
+          const int64_t wa = (int64_t)(A.k - 3) * (A.r - A.k + 1) * (A.r - A.k + 1);
+          const int64_t wb = (int64_t)(B.k - 3) * (B.r - B.k + 1) * (B.r - B.k + 1);
           return wa > wb;
         });
         const size_t tsz = t == 0 ? sizeof(double) : sizeof(float);
         std::vector<BucketDesc> bks;
         std::vector<GenTask> tasks;
-        for (size_t q = 0; q < G.buckets.size(); ++q) {
-          Bucket& B = P->buckets[G.buckets[q]];
-          const int W = r - B.k + 1;
+        for (size_t q = 0; q < grp.buckets.size(); ++q) {
+          Bucket& B = P->buckets[grp.buckets[q]];
+          const int W = B.r - B.k + 1;
           const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, static_cast<int>(tsz));
           BucketDesc& d = B.desc[t];
           if (need <= kLdsBudget) {
             d.lds_stack = 1;
-            G.lds = std::max(G.lds, static_cast<size_t>(need));
+            grp.lds = std::max(grp.lds, static_cast<size_t>(need));
           } else {
             d.lds_stack = 0;
             if (B.gstack[t] == nullptr) {
@@ -440,8 +527,8 @@ int build_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
           for (int64_t blk = 0; blk < nblk; ++blk)
             tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
         }
-        G.ntasks = (int64_t)tasks.size();
-        P->groups.push_back(std::move(G));
+        grp.ntasks = (int64_t)tasks.size();
+        P->groups.push_back(std::move(grp));
         GenGroup& H = P->groups.back();
         if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
         if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);

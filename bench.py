@@ -131,6 +131,72 @@ def cpu_baseline(w, sample_edges, seed=0):
                        "numpy FP64 AAY + fsum; %.1f s" % (len(pick), w["n"], dt))
 
 
+def bench_batch(a):
+    """256 hypergraphs (n log-uniform in [1e3, 1e5], m = 5n, r uniform in
+    {3..12}, P(k) ~ k^-2.5 on [2, r], uniform membership), each restricted to
+    its largest component, in one plan: batched STTSV throughput before and
+    after autotuning, batched solve to 1e-8, and the sum of the per-graph
+    solves for comparison."""
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import workloads as wl
+    log("[bench] batched workload: %d graphs" % a.batch_graphs)
+    gs = []
+    for g in range(a.batch_graphs):
+        w = wl.batch_graph(g)
+        e2, i2, n2, _ = wl.largest_component(w["eptr"], w["eidx"], w["n"])
+        gs.append((e2, i2, n2, w["r"]))
+    ntot = sum(g[2] for g in gs)
+    mtot = sum(len(g[0]) - 1 for g in gs)
+    t0 = time.perf_counter()
+    pb = st.Plan.batch(gs)
+    plan_s = time.perf_counter() - t0
+    xd = torch.ones(ntot, dtype=torch.float64, device="cuda")
+    yd = torch.empty_like(xd)
+    res = {"graphs": len(gs), "n_total": ntot, "m_total": mtot, "plan_s": plan_s}
+
+    def rate(prec):
+        for _ in range(a.warmup):
+            pb.apply(xd, yd, precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(a.steps):
+            pb.apply(xd, yd, precision=prec)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / a.steps
+    for prec in ("fp64", "fp32"):
+        dt = rate(prec)
+        res["sttsv_%s" % prec] = {"ms": dt * 1e3, "hyperedges_per_s": mtot / dt}
+    t0 = time.perf_counter()
+    res["autotune_decisions"] = pb.autotune(xd, reps=3)
+    res["autotune_s"] = time.perf_counter() - t0
+    for prec in ("fp64", "fp32"):
+        dt = rate(prec)
+        res["sttsv_%s_tuned" % prec] = {"ms": dt * 1e3, "hyperedges_per_s": mtot / dt}
+    for sched in ("fp64", "fp32_fp64"):
+        pb.solve_batch(tol=1e-8, schedule=sched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infos = pb.solve_batch(tol=1e-8, schedule=sched)
+        dt = time.perf_counter() - t0
+        its = [i["iterations"] for i in infos]
+        res["solve_batch_%s" % sched] = {"seconds": dt, "iters_min": min(its), "iters_max": max(its),
+                                         "all_converged": all(i["converged"] for i in infos)}
+        log("[bench]   batched solve %s: %.4f s (iterations %d..%d)" % (sched, dt, min(its), max(its)))
+    pb.close()
+    tot = 0.0
+    for (e2, i2, n2, r2) in gs:
+        with st.Plan(e2, i2, n2, r2) as p1:
+            p1.solve(tol=1e-8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p1.solve(tol=1e-8)
+            tot += time.perf_counter() - t0
+    res["solve_single_sum_fp64_s"] = tot
+    log("[bench]   sum of %d single-graph solves: %.4f s" % (len(gs), tot))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-edges", type=int, default=300000)
     ap.add_argument("--stage-reps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=256)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the STTSV path is built and measured on a single "
@@ -235,6 +303,8 @@ def main():
                                     criterion=info["criterion"])
                 log("[bench]   solve %s: %.4f s, %d iterations" % (sched, dt, info["iterations"]))
         out["solve"] = solve
+    if not a.no_batch:
+        out["batched"] = bench_batch(a)
     if not a.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_edges)

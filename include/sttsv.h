@@ -126,6 +126,24 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
                       int32_t cap, int32_t* nstages, int32_t* kinds, int32_t* sizes,
                       int64_t* counts, float* ms);
 
+/*
+ * sttsv_plan_autotune -- per size bucket and series type, time the kernel
+ * variants that compute bitwise-identical contributions (register-resident
+ * vs generic kernel for 4 <= |e| <= 7; suffix stack in LDS vs global memory
+ * for the generic kernel) on the device and keep the fastest.  Tuning never
+ * changes any bit of y.
+ *   x           device, double[n]: a representative input (e.g. the start
+ *               vector of a solve); only read.
+ *   reps        >= 1 timed launches per candidate (median taken).
+ *   cache_path  host string or NULL: text file of earlier choices, keyed by
+ *               (series type, r, |e|, round(log2 edges)); choices found there
+ *               are applied without timing, new ones are appended.
+ *   tuned       host, nullable: number of (bucket, type) pairs decided.
+ * Synchronous; drops the solver's captured hipGraph (rebuilt on next solve).
+ */
+int sttsv_plan_autotune(sttsv_plan_t plan, const double* x, int32_t reps, const char* cache_path,
+                        int32_t* tuned);
+
 /* ---- H-eigenvector centrality (Alg. 1) ------------------------------- */
 
 /* Precision schedules of the solver. */

@@ -134,6 +134,15 @@ class Plan:
             _lib.check(rc)
         return out, d
 
+    def autotune(self, x, reps=5, cache_path=None):
+        """Pick the fastest bitwise-equivalent kernel variants per bucket
+        (``sttsv_plan_autotune``); returns the number of decisions."""
+        xp = _dev_ptr(x, self.n, "x")
+        n = ctypes.c_int32()
+        cp = cache_path.encode() if cache_path else None
+        _lib.check(self._lib.sttsv_plan_autotune(self._h, xp, int(reps), cp, ctypes.byref(n)))
+        return n.value
+
     # ------------------------------------------------------- introspection
     def info(self):
         pi = _lib.PlanInfo()

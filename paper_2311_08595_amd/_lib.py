@@ -31,7 +31,7 @@ Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
            "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
-           "sttsv_plan_graph_info",
+           "sttsv_plan_graph_info", "sttsv_plan_autotune",
            "sttsv_plan_get_info", "sttsv_plan_query", "sttsv_plan_destroy", "sttsv_strerror"]
 
 
@@ -96,6 +96,7 @@ def load(path=None):
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]
     lib.heigvec_solve_ex.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]
+    lib.sttsv_plan_autotune.argtypes = [P, P, i32, ctypes.c_char_p, ctypes.POINTER(i32)]
     lib.sttsv_plan_batch.argtypes = [i32, P, ctypes.POINTER(SttsvOpts), ctypes.POINTER(P)]
     lib.heigvec_solve_batch.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, P]
     lib.sttsv_plan_graph_info.argtypes = [P, i32, ctypes.POINTER(GraphInfo)]

@@ -22,7 +22,7 @@ ARCH = os.environ.get("STTSV_ARCH", "gfx950")
 
 HIP_SOURCES = (["edge_part%d.hip" % i for i in range(8)] + ["edge_gen%d.hip" % i for i in range(8)]
                + ["apply.hip", "reduce.hip", "nqz.hip"])
-CXX_SOURCES = ["plan.cpp", "api.cpp"]
+CXX_SOURCES = ["plan.cpp", "api.cpp", "tune.cpp"]
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off"]
 
 
@@ -41,18 +41,34 @@ def _run(cmd):
     return out
 
 
-def build(jobs=None, verbose=False):
+def _stale(src, obj):
+    """True if obj is missing or older than src or any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".inc"))]
+    deps.append(os.path.join(ROOT, "include", "sttsv.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs=None, verbose=False, incremental=False):
+    """Compile every translation unit (all of them unless ``incremental``)
+    and link libsttsv.so."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     inc = ["-I", CSRC, "-I", os.path.join(ROOT, "include")]
     cmds = []
     for s in HIP_SOURCES:
+        src, obj = os.path.join(CSRC, s), os.path.join(BUILD, s + ".o")
+        if incremental and not _stale(src, obj):
+            continue
         cmds.append([hipcc, "-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-                     *DEVICE_FLAGS, *inc, "-c", os.path.join(CSRC, s),
-                     "-o", os.path.join(BUILD, s + ".o")])
+                     *DEVICE_FLAGS, *inc, "-c", src, "-o", obj])
     for s in CXX_SOURCES:
-        cmds.append([hipcc, "-O2", "-std=c++17", "-fPIC", *inc, "-c", os.path.join(CSRC, s),
-                     "-o", os.path.join(BUILD, s + ".o")])
+        src, obj = os.path.join(CSRC, s), os.path.join(BUILD, s + ".o")
+        if incremental and not _stale(src, obj):
+            continue
+        cmds.append([hipcc, "-O2", "-std=c++17", "-fPIC", *inc, "-c", src, "-o", obj])
     jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, cmds):
@@ -69,8 +85,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("-i", "--incremental", action="store_true",
+                    help="recompile only translation units older than their sources")
     a = ap.parse_args()
-    print(build(a.j, a.v))
+    print(build(a.j, a.v, a.incremental))
 
 
 if __name__ == "__main__":

@@ -118,6 +118,12 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
   });
 }
 
+int sttsv_plan_autotune(sttsv_plan_t plan, const double* x, int32_t reps, const char* cache_path,
+                        int32_t* tuned) {
+  if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
+  return guarded([&] { return sttsv::autotune(*plan->p, x, reps, cache_path, tuned); });
+}
+
 int sttsv_apply(sttsv_plan_t plan, const double* x, double* y) {
   if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
   return sttsv_apply_prec(plan, x, y, plan->p->precision);

@@ -26,7 +26,8 @@ constexpr int kChunk = 32;               // reduction chunk length (fixed: part 
 constexpr int kGenRanges = 8;            // window ranges of the fused generic kernels
 constexpr int kGenLo[kGenRanges] = {1, 9, 17, 25, 33, 41, 49, 57};
 constexpr int kGenHi[kGenRanges] = {8, 16, 24, 32, 40, 48, 56, 63};
-constexpr int64_t kLdsBudget = 40 * 1024;  // LDS per generic block (>= 4 blocks per CU)
+constexpr int64_t kLdsBudget = 40 * 1024;  // LDS per generic block by default (>= 4 blocks per CU)
+constexpr int64_t kLdsMax = 64 * 1024;     // largest LDS per generic block the tuner may choose
 
 // Generic kernel: suffix checkpoint interval C for window W and series size
 // tsz bytes (C + 2 live series within about 160 VGPRs, at most 4), and the
@@ -107,6 +108,7 @@ struct Bucket {
   void* gstack[2] = {nullptr, nullptr};  // generic-kernel global stacks [fp64, fp32]
   BucketDesc desc[2];     // [fp64 series, fp32 series]
   int small_kind[2] = {-1, -1};          // SmallKind, or -1: generic / k = 1
+  int lds_pref[2] = {-1, -1};            // generic stack placement: -1 auto, 0 global, 1 LDS
 };
 
 // A fused generic launch: all generic buckets of one precision whose window
@@ -119,6 +121,7 @@ struct GenGroup {
   size_t lds = 0;
   BucketDesc* d_bks = nullptr;
   GenTask* d_tasks = nullptr;
+  int64_t bytes = 0;
   std::vector<int> buckets;
 };
 
@@ -191,6 +194,7 @@ hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int prec
                         const int32_t* done, hipStream_t s);
 void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t* size, int64_t* count);
 void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
+int build_groups(Plan& p);    // (re)builds the fused generic groups (plan.cpp)
 // The edge launches of one precision (per-graph skip flags, nullable), and
 // the reduction alone: the solver runs both precisions' edge launches then
 // one reduction per iteration.
@@ -201,6 +205,9 @@ hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t
 // reduction kernels (reduce.hip)
 hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
                                const int32_t* done, hipStream_t s);
+
+// autotuner (tune.cpp)
+int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t* tuned);
 
 // solver (nqz.hip): every graph of the plan; infos has one entry per graph
 int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, double* x_out,

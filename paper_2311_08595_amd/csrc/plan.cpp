@@ -225,6 +225,79 @@ bool connected_graph(const GraphIn& g, const std::vector<int64_t>& deg) {
 
 }  // namespace
 
+// Fused generic launches: every bucket of size >= 4 without a per-bucket
+// kernel, grouped by (launch sequence, series type, window range).  Frees
+// and rebuilds the groups; stage lists must be rebuilt afterwards.
+int build_groups(Plan& P) {
+  for (auto& g : P.groups) {
+    (void)hipFree(g.d_bks);
+    (void)hipFree(g.d_tasks);
+    P.device_bytes -= g.bytes;
+  }
+  P.groups.clear();
+  int rc = STTSV_OK;
+  for (int seq = 0; seq < 2; ++seq) {
+    for (int rg = 0; rg < kGenRanges; ++rg) {
+      for (int t = 0; t < 2; ++t) {
+        GenGroup grp;
+        grp.range = rg;
+        grp.seq = seq;
+        grp.f64 = t == 0;
+        for (size_t b = 0; b < P.buckets.size(); ++b) {
+          const Bucket& B = P.buckets[b];
+          const int type = (seq == 0 || !B.fp32_ok || B.k == 1) ? 0 : 1;
+          if (type != t || B.k < 4 || B.small_kind[t] >= 0) continue;
+          if (gen_range_of(B.r - B.k + 1) != rg) continue;
+          grp.buckets.push_back(static_cast<int>(b));
+        }
+        if (grp.buckets.empty()) continue;
+        // longest per-edge work first, so the slow blocks start early
+        std::stable_sort(grp.buckets.begin(), grp.buckets.end(), [&](int a, int b) {
+          const Bucket& A = P.buckets[a];
+          const Bucket& B = P.buckets[b];
+          const int64_t wa = (int64_t)(A.k - 3) * (A.r - A.k + 1) * (A.r - A.k + 1);
+          const int64_t wb = (int64_t)(B.k - 3) * (B.r - B.k + 1) * (B.r - B.k + 1);
+          return wa > wb;
+        });
+        const size_t tsz = t == 0 ? sizeof(double) : sizeof(float);
+        std::vector<BucketDesc> bks;
+        std::vector<GenTask> tasks;
+        for (size_t q = 0; q < grp.buckets.size(); ++q) {
+          Bucket& B = P.buckets[grp.buckets[q]];
+          const int W = B.r - B.k + 1;
+          const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, static_cast<int>(tsz));
+          BucketDesc& d = B.desc[t];
+          const bool use_lds = B.lds_pref[t] >= 0 ? B.lds_pref[t] == 1 && need <= kLdsMax : need <= kLdsBudget;
+          if (use_lds) {
+            d.lds_stack = 1;
+            grp.lds = std::max(grp.lds, static_cast<size_t>(need));
+          } else {
+            d.lds_stack = 0;
+            if (B.gstack[t] == nullptr) {
+              const size_t bytes = (size_t)kg_stack_bytes(B.k, W, static_cast<int>(tsz)) * (size_t)B.m;
+              if (hipMalloc(&B.gstack[t], bytes) != hipSuccess) return STTSV_ENOMEM;
+              P.device_bytes += (int64_t)bytes;
+            }
+            d.gstack = B.gstack[t];
+          }
+          bks.push_back(d);
+          const int64_t nblk = (B.m + kGenBlock - 1) / kGenBlock;
+          for (int64_t blk = 0; blk < nblk; ++blk)
+            tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
+        }
+        grp.ntasks = (int64_t)tasks.size();
+        P.groups.push_back(std::move(grp));
+        GenGroup& H = P.groups.back();
+        const int64_t before = P.device_bytes;
+        if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P.device_bytes)) != STTSV_OK) return rc;
+        if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P.device_bytes)) != STTSV_OK) return rc;
+        H.bytes = P.device_bytes - before;
+      }
+    }
+  }
+  return STTSV_OK;
+}
+
 int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   if (G < 1 || gs == nullptr || out == nullptr) return STTSV_EINVAL;
   if (opts != nullptr && opts->precision != STTSV_PREC_FP64 && opts->precision != STTSV_PREC_FP32)
@@ -479,62 +552,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       B.small_kind[t] = kind;
     }
   }
-  for (int seq = 0; seq < 2; ++seq) {
-    for (int rg = 0; rg < kGenRanges; ++rg) {
-      for (int t = 0; t < 2; ++t) {
-        GenGroup grp;
-        grp.range = rg;
-        grp.seq = seq;
-        grp.f64 = t == 0;
-        for (size_t b = 0; b < P->buckets.size(); ++b) {
-          const Bucket& B = P->buckets[b];
-          const int type = (seq == 0 || !B.fp32_ok || B.k == 1) ? 0 : 1;
-          if (type != t || B.k < 4 || B.small_kind[t] >= 0) continue;
-          if (gen_range_of(B.r - B.k + 1) != rg) continue;
-          grp.buckets.push_back(static_cast<int>(b));
-        }
-        if (grp.buckets.empty()) continue;
-        // longest per-edge work first, so the slow blocks start early
-        std::stable_sort(grp.buckets.begin(), grp.buckets.end(), [&](int a, int b) {
-          const Bucket& A = P->buckets[a];
-          const Bucket& B = P->buckets[b];
-          const int64_t wa = (int64_t)(A.k - 3) * (A.r - A.k + 1) * (A.r - A.k + 1);
-          const int64_t wb = (int64_t)(B.k - 3) * (B.r - B.k + 1) * (B.r - B.k + 1);
-          return wa > wb;
-        });
-        const size_t tsz = t == 0 ? sizeof(double) : sizeof(float);
-        std::vector<BucketDesc> bks;
-        std::vector<GenTask> tasks;
-        for (size_t q = 0; q < grp.buckets.size(); ++q) {
-          Bucket& B = P->buckets[grp.buckets[q]];
-          const int W = B.r - B.k + 1;
-          const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, static_cast<int>(tsz));
-          BucketDesc& d = B.desc[t];
-          if (need <= kLdsBudget) {
-            d.lds_stack = 1;
-            grp.lds = std::max(grp.lds, static_cast<size_t>(need));
-          } else {
-            d.lds_stack = 0;
-            if (B.gstack[t] == nullptr) {
-              const size_t bytes = (size_t)kg_stack_bytes(B.k, W, static_cast<int>(tsz)) * (size_t)B.m;
-              if (hipMalloc(&B.gstack[t], bytes) != hipSuccess) return fail(STTSV_ENOMEM);
-              P->device_bytes += (int64_t)bytes;
-            }
-            d.gstack = B.gstack[t];
-          }
-          bks.push_back(d);
-          const int64_t nblk = (B.m + kGenBlock - 1) / kGenBlock;
-          for (int64_t blk = 0; blk < nblk; ++blk)
-            tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
-        }
-        grp.ntasks = (int64_t)tasks.size();
-        P->groups.push_back(std::move(grp));
-        GenGroup& H = P->groups.back();
-        if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
-        if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
-      }
-    }
-  }
+  if ((rc = build_groups(*P)) != STTSV_OK) return fail(rc);
   build_stages(*P);
   if (hipDeviceSynchronize() != hipSuccess) return fail(STTSV_EHIP);
   *out = P;

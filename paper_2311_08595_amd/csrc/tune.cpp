@@ -1,0 +1,171 @@
+// Autotuner: picks, per size bucket and series type, among kernel variants
+// that compute bitwise-identical contributions (so tuning never changes y):
+//   * 4 <= k <= 7: register-resident kernel vs the generic kernel;
+//   * generic buckets: suffix stack in LDS vs in global memory.
+// Each candidate is launched alone on the plan's stream with the caller's x
+// and timed with hipEvents (median of reps); the choices are kept in the plan
+// and in a cache keyed by (series type, r, k, round(log2 m)), which can be
+// read from and appended to a text file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace sttsv {
+namespace {
+
+struct Choice {
+  int use_kr;   // -1 not applicable, 0 generic, 1 register-resident
+  int lds;      // -1 not applicable, 0 global stack, 1 LDS stack
+};
+
+std::mutex g_mu;
+std::map<std::string, Choice> g_cache;
+
+std::string key_of(int t, const Bucket& B) {
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "t%d_r%d_k%d_m%d", t, B.r, B.k,
+                static_cast<int>(std::lround(std::log2(std::max<double>(1.0, (double)B.m)))));
+  return buf;
+}
+
+void load_cache(const char* path) {
+  if (path == nullptr) return;
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return;
+  char key[96];
+  int a = 0, b = 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  while (std::fscanf(f, "%95s %d %d", key, &a, &b) == 3) g_cache[key] = Choice{a, b};
+  std::fclose(f);
+}
+
+void append_cache(const char* path, const std::string& key, const Choice& c) {
+  if (path == nullptr) return;
+  FILE* f = std::fopen(path, "a");
+  if (f == nullptr) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), c.use_kr, c.lds);
+  std::fclose(f);
+}
+
+template <typename F>
+float time_median(F&& launch, int reps, hipStream_t s) {
+  std::vector<float> t;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 1e30f;
+  (void)launch();                                   // warm-up
+  for (int i = 0; i < reps; ++i) {
+    float ms = 0.f;
+    if (hipEventRecord(a, s) != hipSuccess || launch() != hipSuccess || hipEventRecord(b, s) != hipSuccess ||
+        hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      ms = 1e30f;
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+// A one-bucket generic launch with the given stack placement.
+float time_generic(Plan& p, Bucket& B, int t, bool lds, const EdgeCall& c, int reps) {
+  const EdgeTables& tab = edge_tables();
+  const int W = B.r - B.k + 1;
+  const int tsz = t == 0 ? 8 : 4;
+  const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, tsz);
+  if (lds && need > kLdsMax) return 1e30f;
+  BucketDesc d = B.desc[t];
+  void* tmp = nullptr;
+  d.lds_stack = lds ? 1 : 0;
+  if (!lds) {
+    if (B.gstack[t] != nullptr) {
+      d.gstack = B.gstack[t];
+    } else {
+      if (hipMalloc(&tmp, (size_t)kg_stack_bytes(B.k, W, tsz) * (size_t)B.m) != hipSuccess) return 1e30f;
+      d.gstack = tmp;
+    }
+  }
+  std::vector<GenTask> tasks;
+  for (int64_t blk = 0; blk < (B.m + kGenBlock - 1) / kGenBlock; ++blk)
+    tasks.push_back(GenTask{0, static_cast<int32_t>(blk)});
+  BucketDesc* d_b = nullptr;
+  GenTask* d_t = nullptr;
+  float ms = 1e30f;
+  if (hipMalloc(&d_b, sizeof(BucketDesc)) == hipSuccess &&
+      hipMalloc(&d_t, sizeof(GenTask) * tasks.size()) == hipSuccess &&
+      hipMemcpy(d_b, &d, sizeof(BucketDesc), hipMemcpyHostToDevice) == hipSuccess &&
+      hipMemcpy(d_t, tasks.data(), sizeof(GenTask) * tasks.size(), hipMemcpyHostToDevice) == hipSuccess) {
+    const GenLaunchFn fn = t == 0 ? tab.gen64[gen_range_of(W)] : tab.gen32[gen_range_of(W)];
+    const size_t ldsb = lds ? static_cast<size_t>(need) : 0;
+    if (fn != nullptr)
+      ms = time_median([&] { return fn(c, d_b, d_t, (int64_t)tasks.size(), ldsb, p.stream); }, reps, p.stream);
+  }
+  (void)hipFree(d_b);
+  (void)hipFree(d_t);
+  (void)hipFree(tmp);
+  return ms;
+}
+
+}  // namespace
+
+int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t* tuned) {
+  if (x == nullptr || reps < 1) return STTSV_EINVAL;
+  load_cache(cache_path);
+  const EdgeTables& tab = edge_tables();
+  const EdgeCall c{x, p.d_contrib, nullptr, nullptr};
+  int count = 0;
+  for (Bucket& B : p.buckets) {
+    if (B.k < 4) continue;
+    const int W = B.r - B.k + 1;
+    for (int t = 0; t < 2; ++t) {
+      if (t == 1 && !B.fp32_ok) continue;
+      const std::string key = key_of(t, B);
+      Choice ch{-1, -1};
+      bool cached = false;
+      {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+          ch = it->second;
+          cached = true;
+        }
+      }
+      const auto& small = t == 0 ? tab.small64 : tab.small32;
+      const SmallLaunchFn kr = (B.k <= 7 && !(p.flags & STTSV_FLAG_GENERIC_ONLY)) ? small[SK_R4 + (B.k - 4)][W] : nullptr;
+      if (!cached) {
+        const float g_lds = time_generic(p, B, t, true, c, reps);
+        const float g_glb = time_generic(p, B, t, false, c, reps);
+        const float g_best = std::min(g_lds, g_glb);
+        ch.lds = g_lds <= g_glb ? 1 : 0;
+        ch.use_kr = -1;
+        if (kr != nullptr) {
+          const BucketDesc d = B.desc[t];
+          const float t_kr = time_median([&] { return kr(c, d, p.stream); }, reps, p.stream);
+          ch.use_kr = t_kr <= g_best ? 1 : 0;
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = ch;
+        append_cache(cache_path, key, ch);
+      }
+      if (kr != nullptr && ch.use_kr >= 0) B.small_kind[t] = ch.use_kr == 1 ? SK_R4 + (B.k - 4) : -1;
+      if (ch.lds >= 0) B.lds_pref[t] = ch.lds;
+      ++count;
+    }
+  }
+  if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
+  free_solver(p);                 // the captured launch sequence changes
+  const int rc = build_groups(p);
+  if (rc != STTSV_OK) return rc;
+  build_stages(p);
+  if (tuned != nullptr) *tuned = count;
+  return STTSV_OK;
+}
+
+}  // namespace sttsv

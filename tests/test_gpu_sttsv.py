@@ -211,3 +211,24 @@ def test_kernel_variants_bitwise_equal(torch_cuda, prec):
             a = p1.apply(xd, precision=prec).cpu().numpy()
             b = p2.apply(xd, precision=prec).cpu().numpy()
         assert a.tobytes() == b.tobytes(), r
+
+
+def test_autotune_keeps_bits(tmp_path):
+    # the tuner only chooses among bitwise-identical variants
+    import paper_2311_08595_amd as st
+    import torch
+    for prec in ("fp64", "fp32"):
+        w = wl.zipf_powerlaw(seed=14, n=30000, m=120000)
+        xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+        cache = str(tmp_path / "tune.txt")
+        with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as plan:
+            before = plan.apply(xd, precision=prec).cpu().numpy()
+            assert plan.autotune(xd, reps=3, cache_path=cache) > 0
+            after = plan.apply(xd, precision=prec).cpu().numpy()
+        assert before.tobytes() == after.tobytes()
+        # second plan reads the cache (no timing) and still agrees
+        with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as plan2:
+            plan2.autotune(xd, reps=1, cache_path=cache)
+            again = plan2.apply(xd, precision=prec).cpu().numpy()
+        assert again.tobytes() == before.tobytes()
+        assert len(open(cache).read().split()) > 0

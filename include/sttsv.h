@@ -246,6 +246,58 @@ typedef struct {
 
 int sttsv_plan_graph_info(sttsv_plan_t plan, int32_t g, sttsv_graph_info* info);
 
+/* ---- learned warm start ------------------------------------------------ */
+/*
+ * A small hypergraph message-passing network predicts log x (up to a
+ * constant) for the H-eigenvector centrality, to start Alg. 1 closer to its
+ * fixed point.  Hidden width 64; features of vertex v: log(1+d_v), mean
+ * log|e| over its edges, log(d_v)/(r-1), log(1 + sum over its edges of
+ * (|e|-1)).  H0 = relu(F W0 + b0); two layers of {vertex->edge mean,
+ * edge->vertex mean A, H = relu([H, A] W + b)}; score s = H2 w_out + b_out;
+ * warm start x0 = exp(s - max s)/sum.  Dense products: BF16 inputs and
+ * weights on the matrix cores, FP32 accumulation; FP32 master weights and
+ * Adam.  Deterministic (fixed-order reductions).
+ *
+ * Parameters are one packed FP32 vector of STTSV_MPNN_NPARAM entries:
+ * W0 (16 x 64, row-major, rows 4..15 unused = 0), b0 (64), W1 (128 x 64),
+ * b1 (64), W2 (128 x 64), b2 (64), w_out (64), b_out (1).
+ * All calls run on the default stream and are asynchronous unless stated.
+ */
+#define STTSV_MPNN_HIDDEN 64
+#define STTSV_MPNN_NPARAM 17665
+
+typedef struct sttsv_mpnn_graph_s* sttsv_mpnn_graph_t;
+typedef struct sttsv_mpnn_s* sttsv_mpnn_t;
+
+/* Device copy of a hypergraph for the network (host CSR as in sttsv_plan;
+ * r >= 2 is only used by the features).  Synchronous.  EINVAL / ENOMEM. */
+int sttsv_mpnn_graph(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, int32_t r,
+                     sttsv_mpnn_graph_t* out);
+int sttsv_mpnn_graph_destroy(sttsv_mpnn_graph_t g);
+
+/* Network with initial parameters (host, STTSV_MPNN_NPARAM floats); Adam
+ * moments start at 0.  Synchronous. */
+int sttsv_mpnn_create(const float* params, sttsv_mpnn_t* out);
+int sttsv_mpnn_destroy(sttsv_mpnn_t net);
+
+/* Copy the current parameters and/or the last gradients to host memory
+ * (either pointer nullable, STTSV_MPNN_NPARAM floats each).  Synchronous. */
+int sttsv_mpnn_params(sttsv_mpnn_t net, float* params_out, float* grads_out);
+
+/* Scores s (device float[n], nullable to keep them internal). */
+int sttsv_mpnn_forward(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, float* scores);
+
+/* Forward + loss L = mean(u^2), u = (s - mean s) - (log x* - mean log x*),
+ * + backward: gradients kept in the network.  x_star device double[n] > 0.
+ * loss host, nullable (when given the call synchronises). */
+int sttsv_mpnn_loss_grad(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, const double* x_star, float* loss);
+
+/* One Adam step with the stored gradients (bias-corrected). */
+int sttsv_mpnn_adam(sttsv_mpnn_t net, float lr, float beta1, float beta2, float eps);
+
+/* Warm start x0 = exp(s - max s) / sum (device double[n], > 0, l1 norm 1). */
+int sttsv_mpnn_warm_start(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, double* x0);
+
 /* ---- plan introspection (host copies; used to check the layout) ------- */
 #define STTSV_Q_PERM        0  /* int64[m]   input index of canonical edge c      */
 #define STTSV_Q_MEM         1  /* int64[nnz] member slots (original vertex ids)   */

@@ -21,6 +21,8 @@ STTSV_ENUMERIC = -5
 STTSV_EHIP = -6
 STTSV_ENOTSUP = -7
 STTSV_MAX_ORDER = 64
+MPNN_NPARAM = 17665
+MPNN_HIDDEN = 64
 FLAG_GENERIC_ONLY = 1
 
 PREC = {"fp64": 0, "fp32": 1}
@@ -32,6 +34,9 @@ Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, 
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
            "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
            "sttsv_plan_graph_info", "sttsv_plan_autotune",
+           "sttsv_mpnn_graph", "sttsv_mpnn_graph_destroy", "sttsv_mpnn_create", "sttsv_mpnn_destroy",
+           "sttsv_mpnn_params", "sttsv_mpnn_forward", "sttsv_mpnn_loss_grad", "sttsv_mpnn_adam",
+           "sttsv_mpnn_warm_start",
            "sttsv_plan_get_info", "sttsv_plan_query", "sttsv_plan_destroy", "sttsv_strerror"]
 
 
@@ -96,6 +101,16 @@ def load(path=None):
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]
     lib.heigvec_solve_ex.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]
+    f32 = ctypes.c_float
+    lib.sttsv_mpnn_graph.argtypes = [P, P, i64, i32, i32, ctypes.POINTER(P)]
+    lib.sttsv_mpnn_graph_destroy.argtypes = [P]
+    lib.sttsv_mpnn_create.argtypes = [P, ctypes.POINTER(P)]
+    lib.sttsv_mpnn_destroy.argtypes = [P]
+    lib.sttsv_mpnn_params.argtypes = [P, P, P]
+    lib.sttsv_mpnn_forward.argtypes = [P, P, P]
+    lib.sttsv_mpnn_loss_grad.argtypes = [P, P, P, ctypes.POINTER(f32)]
+    lib.sttsv_mpnn_adam.argtypes = [P, f32, f32, f32, f32]
+    lib.sttsv_mpnn_warm_start.argtypes = [P, P, P]
     lib.sttsv_plan_autotune.argtypes = [P, P, i32, ctypes.c_char_p, ctypes.POINTER(i32)]
     lib.sttsv_plan_batch.argtypes = [i32, P, ctypes.POINTER(SttsvOpts), ctypes.POINTER(P)]
     lib.heigvec_solve_batch.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, P]

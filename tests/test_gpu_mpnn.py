@@ -1,0 +1,101 @@
+"""Warm-start network on the GPU against the FP64 oracle (oracle/mpnn_ref.py).
+
+The oracle is run with the same bfloat16 roundings the kernels make, so the
+remaining differences come from FP32 accumulation (and the rare bf16 rounding
+that an FP32-vs-FP64 difference flips); bounds are norm-wise.
+"""
+import numpy as np
+import pytest
+
+from oracle import mpnn_ref as mr
+from paper_2311_08595_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KF, HID = 16, 64
+
+
+def to_gpu_params(p):
+    W0 = np.zeros((KF, HID))
+    W0[:4] = p["W0"]
+    parts = [W0, p["b0"], p["W1"], p["b1"], p["W2"], p["b2"], p["wout"], p["bout"]]
+    return np.concatenate([np.asarray(a).ravel() for a in parts]).astype(np.float32)
+
+
+def from_gpu_vec(v):
+    v = np.asarray(v, dtype=np.float64)
+    o = 0
+    out = {}
+    for name, shp in [("W0", (KF, HID)), ("b0", (HID,)), ("W1", (2 * HID, HID)), ("b1", (HID,)),
+                      ("W2", (2 * HID, HID)), ("b2", (HID,)), ("wout", (HID,)), ("bout", (1,))]:
+        size = int(np.prod(shp))
+        out[name] = v[o:o + size].reshape(shp)
+        o += size
+    out["W0pad"] = out["W0"][4:]
+    out["W0"] = out["W0"][:4]
+    return out
+
+
+def _graph(seed=4, n=400, m=1600, r=9):
+    w = wl.zipf_powerlaw(seed=seed, n=n, m=m, kmax=r)
+    e, i, nl, _ = wl.largest_component(w["eptr"], w["eidx"], w["n"])
+    return e, i, nl, r
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_forward_and_gradients_match_oracle():
+    import torch
+    from paper_2311_08595_amd.warmstart import MpnnGraph, WarmStartNet
+    e, i, n, r = _graph()
+    rng = np.random.default_rng(1)
+    p = {k: rng.normal(0, 0.2, shp) for k, shp in mr.PARAM_SHAPES}
+    # round the weights to what FP32 storage holds, as the GPU sees them
+    p = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()}
+    xs = np.exp(rng.normal(0, 0.4, n))
+    xs /= xs.sum()
+    g_ref = mr.Graph(e, i, n, r)
+    s_ref, cache = mr.forward(p, g_ref, bf=True)
+    L_ref, ds = mr.loss(s_ref, xs)
+    gr = mr.backward(p, g_ref, cache, ds, bf=True)
+
+    net = WarmStartNet(params=to_gpu_params(p))
+    g = MpnnGraph(e, i, n, r)
+    s = net.scores(g).cpu().numpy().astype(np.float64)
+    assert _rel(s - s.mean(), s_ref - s_ref.mean()) <= 2e-3, _rel(s, s_ref)
+    L = net.loss_grad(g, torch.tensor(xs, dtype=torch.float64, device="cuda"))
+    assert abs(L - L_ref) <= 1e-2 * L_ref, (L, L_ref)
+    G = from_gpu_vec(net.grads())
+    for name in ("W0", "b0", "W1", "b1", "W2", "b2", "wout"):
+        err = _rel(G[name], gr[name])
+        print(name, "rel err %.2e" % err, flush=True)
+        assert err <= 2e-2, (name, err)
+    assert np.all(G["W0pad"] == 0.0)
+
+
+def test_training_reduces_loss_and_warm_start_is_valid():
+    import torch
+    from paper_2311_08595_amd import Plan
+    from paper_2311_08595_amd.warmstart import MpnnGraph, WarmStartNet, train
+    data = []
+    for s in range(6):
+        e, i, n, r = _graph(seed=40 + s, n=1500, m=6000, r=12)
+        with Plan(e, i, n, r) as p:
+            x, _ = p.solve(tol=1e-9)
+        data.append((MpnnGraph(e, i, n, r), x, 0))
+    net = WarmStartNet(seed=3)
+    before = np.mean([net.loss_grad(g, x) for g, x, _ in data])
+    hist = train(net, data, epochs=6, lr=3e-3)
+    after = np.mean([net.loss_grad(g, x) for g, x, _ in data])
+    assert after < 0.7 * before, (before, after, hist)
+    g, x, _ = data[0]
+    x0 = net.warm_start(g).cpu().numpy()
+    assert np.all(x0 > 0) and abs(x0.sum() - 1.0) < 1e-12
+    s = net.scores(g).cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(x0, mr.warm_start(s), rtol=1e-6)
+    # deterministic: same data, same seed -> same weights
+    net2 = WarmStartNet(seed=3)
+    train(net2, data, epochs=6, lr=3e-3)
+    assert net.params().tobytes() == net2.params().tobytes()

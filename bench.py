@@ -183,6 +183,36 @@ def bench_batch(a):
         res["solve_batch_%s" % sched] = {"seconds": dt, "iters_min": min(its), "iters_max": max(its),
                                          "all_converged": all(i["converged"] for i in infos)}
         log("[bench]   batched solve %s: %.4f s (iterations %d..%d)" % (sched, dt, min(its), max(its)))
+    from paper_2311_08595_amd.warmstart import MpnnGraph, WarmStartNet, DEFAULT_WEIGHTS
+    if os.path.exists(DEFAULT_WEIGHTS):
+        net = WarmStartNet.load(DEFAULT_WEIGHTS)
+        mgs = [MpnnGraph(e2, i2, n2, r2) for (e2, i2, n2, r2) in gs]
+        x0 = torch.empty(ntot, dtype=torch.float64, device="cuda")
+
+        def infer():
+            off = 0
+            for mg in mgs:
+                net.warm_start(mg, out=x0[off:off + mg.n])
+                off += mg.n
+        infer()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infer()
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        res["net_inference_s"] = t_inf
+        for sched in ("fp64", "fp32_fp64"):
+            pb.solve_batch(tol=1e-8, schedule=sched, x0=x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos = pb.solve_batch(tol=1e-8, schedule=sched, x0=x0)
+            dt = time.perf_counter() - t0
+            its = [i["iterations"] for i in infos]
+            res["solve_batch_net_start_%s" % sched] = {"seconds": dt + t_inf, "solve_seconds": dt,
+                                                       "iters_min": min(its), "iters_max": max(its),
+                                                       "all_converged": all(i["converged"] for i in infos)}
+            log("[bench]   batched solve %s (learned start): %.4f s incl. %.4f s inference (iterations %d..%d)"
+                % (sched, dt + t_inf, t_inf, min(its), max(its)))
     pb.close()
     tot = 0.0
     for (e2, i2, n2, r2) in gs:
@@ -290,18 +320,47 @@ def main():
     if not a.no_solve:
         log("[bench] largest component + solves")
         e2, i2, n2, _ = wl.largest_component(w["eptr"], w["eidx"], n)
+        solve = {"n_lcc": n2, "m_lcc": len(e2) - 1, "tol": 1e-8}
         with st.Plan(e2, i2, n2, r) as p2:
-            solve = {"n_lcc": n2, "m_lcc": len(e2) - 1, "tol": 1e-8}
-            for sched in ("fp64", "fp32_fp64"):
-                p2.solve(tol=1e-8, schedule=sched)           # warm-up (graph capture)
+            def timed(sched, x0=None, pre=0.0):
+                p2.solve(tol=1e-8, schedule=sched, x0=x0)   # warm-up (graph capture)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                _, info = p2.solve(tol=1e-8, schedule=sched)
+                _, info = p2.solve(tol=1e-8, schedule=sched, x0=x0)
                 dt = time.perf_counter() - t0
-                solve[sched] = dict(seconds=dt, iterations=info["iterations"], iters_fp32=info["iters_fp32"],
-                                    iters_fp64=info["iters_fp64"], lambda_max=info["lambda_max"],
-                                    criterion=info["criterion"])
-                log("[bench]   solve %s: %.4f s, %d iterations" % (sched, dt, info["iterations"]))
+                return dict(seconds=dt + pre, solve_seconds=dt, iterations=info["iterations"],
+                            iters_fp32=info["iters_fp32"], iters_fp64=info["iters_fp64"],
+                            lambda_max=info["lambda_max"], criterion=info["criterion"])
+            for sched in ("fp64", "fp32_fp64"):
+                solve[sched] = timed(sched)
+                log("[bench]   solve %s (uniform start): %.4f s, %d iterations"
+                    % (sched, solve[sched]["seconds"], solve[sched]["iterations"]))
+            # control: degree start d^(1/(r-1)) (the first NQZ iterate from the uniform start)
+            d = np.bincount(i2, minlength=n2).astype(np.float64)
+            xdeg = torch.tensor(d ** (1.0 / (r - 1)), dtype=torch.float64, device="cuda")
+            solve["degree_start_fp64"] = timed("fp64", xdeg)
+            log("[bench]   solve fp64 (degree start): %.4f s, %d iterations"
+                % (solve["degree_start_fp64"]["seconds"], solve["degree_start_fp64"]["iterations"]))
+            # learned warm start (network trained on n=1e4 graphs), inference timed with the solve
+            from paper_2311_08595_amd.warmstart import MpnnGraph, WarmStartNet, DEFAULT_WEIGHTS
+            if os.path.exists(DEFAULT_WEIGHTS):
+                net = WarmStartNet.load(DEFAULT_WEIGHTS)
+                t0 = time.perf_counter()
+                mg = MpnnGraph(e2, i2, n2, r)
+                prep = time.perf_counter() - t0
+                net.warm_start(mg)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x0 = net.warm_start(mg)
+                torch.cuda.synchronize()
+                infer = time.perf_counter() - t0
+                solve["net_graph_prep_s"] = prep
+                solve["net_inference_s"] = infer
+                for sched in ("fp64", "fp32_fp64"):
+                    solve["net_start_" + sched] = timed(sched, x0, pre=infer)
+                    log("[bench]   solve %s (learned start): %.4f s incl. %.4f s inference, %d iterations"
+                        % (sched, solve["net_start_" + sched]["seconds"], infer,
+                           solve["net_start_" + sched]["iterations"]))
         out["solve"] = solve
     if not a.no_batch:
         out["batched"] = bench_batch(a)

@@ -58,6 +58,15 @@ struct Graph {
   float* inv_size = nullptr;  // 1/|e|
   float* inv_deg = nullptr;   // 1/d_v
   uint16_t* X0 = nullptr;     // n x KF features (bf16)
+  // vertex-side sums over E(v) in fixed-shape chunks (level 0 reads edges
+  // through nedge, level l > 0 reads the partial rows of level l-1)
+  static constexpr int kMaxLevels = 6;
+  int nlev = 0;
+  int32_t nchunk[kMaxLevels] = {};
+  int32_t* cstart[kMaxLevels] = {};
+  int32_t* clen[kMaxLevels] = {};
+  int32_t* cdst[kMaxLevels] = {};   // >= 0 vertex (final); < 0: -(partial row)-1
+  int32_t npart[kMaxLevels] = {};   // partial rows written by level l
 };
 
 struct Net {
@@ -78,6 +87,8 @@ struct Net {
   float *s = nullptr, *ds = nullptr;                // n
   float* part = nullptr;                            // partials
   int64_t part_cap = 0;
+  float* vpart[2] = {nullptr, nullptr};             // vertex-sum partial rows (ping-pong)
+  int64_t vpart_cap = 0;
   float* scal = nullptr;                            // small scalars
 };
 
@@ -201,14 +212,39 @@ __global__ void __launch_bounds__(256) edge_mean(Graph g, const float* __restric
   E[e * HD + c] = acc * g.inv_size[e];
 }
 
-// A_v = (1/d_v) sum_{e in E(v)} Ed_e -> bf16 into the right half of X
-__global__ void __launch_bounds__(256) node_mean(Graph g, const float* __restrict__ E, uint16_t* __restrict__ X) {
-  const int64_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
-  if (v >= g.n) return;
+// Vertex-side sums over E(v), one wave per chunk of at most kVChunk terms,
+// lane = feature.  MODE 0 (edge->vertex mean): terms Ed_e, final value
+// bf16(sum / d_v) into the right half of X.  MODE 1 (adjoint of the
+// vertex->edge mean): terms dE_e / |e|, final value added to dH_v.
+constexpr int kVChunk = 128;
+
+template <int MODE>
+__global__ void __launch_bounds__(256) vsum_level(int nchunk, const int32_t* __restrict__ cstart,
+                                                  const int32_t* __restrict__ clen, const int32_t* __restrict__ cdst,
+                                                  const int32_t* __restrict__ nedge, const float* __restrict__ inv_size,
+                                                  const float* __restrict__ inv_deg, const float* __restrict__ src,
+                                                  const float* __restrict__ prev, float* __restrict__ part,
+                                                  uint16_t* __restrict__ X, float* __restrict__ dH) {
+  const int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int f = threadIdx.x & 63;
+  if (c >= nchunk) return;
+  const int32_t st = cstart[c], ln = clen[c], d = cdst[c];
   float acc = 0.f;
-  for (int q = g.nptr[v]; q < g.nptr[v + 1]; ++q) acc += E[(int64_t)g.nedge[q] * HD + c];
-  X[v * 2 * HD + HD + c] = to_bf16(acc * g.inv_deg[v]);
+  if (prev == nullptr) {
+    for (int q = 0; q < ln; ++q) {
+      const int e = nedge[st + q];
+      acc += MODE == 0 ? src[(int64_t)e * HD + f] : src[(int64_t)e * HD + f] * inv_size[e];
+    }
+  } else {
+    for (int q = 0; q < ln; ++q) acc += prev[(int64_t)(st + q) * HD + f];
+  }
+  if (d < 0) {
+    part[(int64_t)(-(int64_t)d - 1) * HD + f] = acc;
+  } else if (MODE == 0) {
+    X[(int64_t)d * 2 * HD + HD + f] = to_bf16(acc * inv_deg[d]);
+  } else {
+    dH[(int64_t)d * HD + f] += acc;
+  }
 }
 
 // adjoint of node_mean: dE_e = sum_{v in e} dA_v / d_v
@@ -222,19 +258,6 @@ __global__ void __launch_bounds__(256) node_mean_T(Graph g, const float* __restr
     acc += dA[(int64_t)v * HD + c] * g.inv_deg[v];
   }
   dE[e * HD + c] = acc;
-}
-
-// adjoint of edge_mean, added: dH_v += sum_{e in E(v)} dE_e / |e|
-__global__ void __launch_bounds__(256) edge_mean_T(Graph g, const float* __restrict__ dE, float* __restrict__ dH) {
-  const int64_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
-  if (v >= g.n) return;
-  float acc = 0.f;
-  for (int q = g.nptr[v]; q < g.nptr[v + 1]; ++q) {
-    const int e = g.nedge[q];
-    acc += dE[(int64_t)e * HD + c] * g.inv_size[e];
-  }
-  dH[v * HD + c] += acc;
 }
 
 // s_v = H2_v . wout + bout  (one wave per vertex)
@@ -394,21 +417,28 @@ __global__ void __launch_bounds__(256) weights_bf16(const float* W, int K, uint1
   wt[j * K + k] = h;
 }
 
-// x0 = exp(s - max s) / sum (double)
-__global__ void __launch_bounds__(256) warm_kernel(const float* s, int n, double* x0) {
+// x0 = exp(s - max s) / sum: block maxima, then exponentials and block
+// sums, then the division (fixed-shape reductions)
+__global__ void __launch_bounds__(256) warm_max(const float* s, int n, double* part) {
   __shared__ double sh[256];
   double mx = -INFINITY;
-  for (int v = threadIdx.x; v < n; v += 256) mx = fmax(mx, double(s[v]));
+  for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) mx = fmax(mx, double(s[v]));
   sh[threadIdx.x] = mx;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
-  mx = sh[0];
-  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) warm_exp(const float* s, int n, const double* part, int nb, double* x0,
+                                                double* psum) {
+  __shared__ double sh[256];
+  double mx = -INFINITY;
+  for (int q = 0; q < nb; ++q) mx = fmax(mx, part[q]);
   double acc = 0.0;
-  for (int v = threadIdx.x; v < n; v += 256) {
+  for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
     const double e = exp(double(s[v]) - mx);
     x0[v] = e;
     acc += e;
@@ -419,8 +449,13 @@ __global__ void __launch_bounds__(256) warm_kernel(const float* s, int n, double
     if (threadIdx.x < o) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + o];
     __syncthreads();
   }
-  const double tot = sh[0];
-  for (int v = threadIdx.x; v < n; v += 256) x0[v] = x0[v] / tot;
+  if (threadIdx.x == 0) psum[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) warm_div(int n, const double* psum, int nb, double* x0) {
+  double tot = 0.0;
+  for (int q = 0; q < nb; ++q) tot += psum[q];
+  for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) x0[v] = x0[v] / tot;
 }
 
 // ------------------------------------------------------------------ host side
@@ -456,6 +491,30 @@ int ensure_workspace(Net& N, const Graph& g) {
   return good ? STTSV_OK : STTSV_ENOMEM;
 }
 
+int ensure_vpart(Net& N, const Graph& g) {
+  int64_t need = 1;
+  for (int l = 0; l < g.nlev; ++l) need = std::max<int64_t>(need, g.npart[l]);
+  if (need <= N.vpart_cap) return STTSV_OK;
+  for (int i = 0; i < 2; ++i) {
+    (void)hipFree(N.vpart[i]);
+    if (!dalloc(&N.vpart[i], (size_t)need * HD)) return STTSV_ENOMEM;
+  }
+  N.vpart_cap = need;
+  return STTSV_OK;
+}
+
+template <int MODE>
+void vertex_sums(Net& N, const Graph& g, const float* src, uint16_t* X, float* dH, hipStream_t s) {
+  for (int l = 0; l < g.nlev; ++l) {
+    const float* prev = l == 0 ? nullptr : N.vpart[(l - 1) & 1];
+    float* part = N.vpart[l & 1];
+    hipLaunchKernelGGL((vsum_level<MODE>), dim3((g.nchunk[l] + 3) / 4), dim3(256), 0, s, g.nchunk[l],
+                       (const int32_t*)g.cstart[l], (const int32_t*)g.clen[l], (const int32_t*)g.cdst[l],
+                       (const int32_t*)g.nedge, (const float*)g.inv_size, (const float*)g.inv_deg, src, prev, part, X,
+                       dH);
+  }
+}
+
 int refresh_bf16(Net& N, hipStream_t s) {
   const int K[3] = {KF, 2 * HD, 2 * HD};
   const int off[3] = {OFF_W0, OFF_W1, OFF_W2};
@@ -467,13 +526,14 @@ int refresh_bf16(Net& N, hipStream_t s) {
 
 int forward(Net& N, const Graph& g, hipStream_t s) {
   int rc = ensure_workspace(N, g);
+  if (rc == STTSV_OK) rc = ensure_vpart(N, g);
   if (rc != STTSV_OK) return rc;
   const dim3 gd((g.n + 63) / 64), ge((g.m + 3) / 4), gv((g.n + 3) / 4);
   hipLaunchKernelGGL((dense_fwd<KF>), gd, dim3(256), 0, s, g.X0, KF, N.wt[0], N.p + OFF_B0, g.n, N.Z[0], N.Hh[0],
                      N.X[1]);
   for (int l = 1; l <= 2; ++l) {
     hipLaunchKernelGGL(edge_mean, ge, dim3(256), 0, s, g, (const float*)N.Hh[l - 1], N.E);
-    hipLaunchKernelGGL(node_mean, gv, dim3(256), 0, s, g, (const float*)N.E, N.X[l]);
+    vertex_sums<0>(N, g, (const float*)N.E, N.X[l], nullptr, s);
     hipLaunchKernelGGL((dense_fwd<2 * HD>), gd, dim3(256), 0, s, N.X[l], 2 * HD, N.wt[l],
                        N.p + (l == 1 ? OFF_B1 : OFF_B2), g.n, N.Z[l], N.Hh[l], l == 1 ? N.X[2] : nullptr);
   }
@@ -509,7 +569,7 @@ int loss_and_grad(Net& N, const Graph& g, const double* xstar, float* loss_host,
     hipLaunchKernelGGL(dense_bwd_dx, gd, dim3(256), 0, s, (const uint16_t*)N.dZb, (const uint16_t*)N.wr[l], g.n,
                        N.dH, N.dA);
     hipLaunchKernelGGL(node_mean_T, ge, dim3(256), 0, s, g, (const float*)N.dA, N.dE);
-    hipLaunchKernelGGL(edge_mean_T, gv, dim3(256), 0, s, g, (const float*)N.dE, N.dH);
+    vertex_sums<1>(N, g, (const float*)N.dE, nullptr, N.dH, s);
   }
   hipLaunchKernelGGL(relu_bwd, gc, dim3(256), 0, s, (const float*)N.dH, (const float*)N.Z[0], cnt, N.dZ, N.dZb);
   hipLaunchKernelGGL((wgrad_tile<KF>), dim3(tiles), dim3(256), 0, s, (const uint16_t*)g.X0, KF, (const float*)N.dZ,
@@ -573,6 +633,56 @@ int sttsv_mpnn_graph(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_
          hipMemcpy(g.eidx, eidx, 4 * nnz, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(g.nptr, np.data(), 4 * ((size_t)n + 1), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(g.nedge, ne.data(), 4 * nnz, hipMemcpyHostToDevice) == hipSuccess;
+  // chunk levels of the vertex-side sums: a vertex's edges in chunks of
+  // kVChunk; if it has several, their partial rows are summed the same way
+  if (good) {
+    std::vector<int64_t> seg_start(n), seg_len(n);
+    std::vector<int32_t> seg_node(n);
+    for (int32_t v = 0; v < n; ++v) {
+      seg_start[v] = np[v];
+      seg_len[v] = np[v + 1] - np[v];
+      seg_node[v] = v;
+    }
+    while (!seg_node.empty() && good) {
+      if (g.nlev == Graph::kMaxLevels) {
+        good = false;
+        break;
+      }
+      std::vector<int32_t> st, ln, ds;
+      std::vector<int64_t> nst, nln;
+      std::vector<int32_t> nnd;
+      int64_t next = 0;
+      for (size_t q = 0; q < seg_node.size(); ++q) {
+        const int64_t d = seg_len[q];
+        const int64_t nch = d <= kVChunk ? 1 : (d + kVChunk - 1) / kVChunk;
+        if (nch == 1) {
+          st.push_back(static_cast<int32_t>(seg_start[q]));
+          ln.push_back(static_cast<int32_t>(d));
+          ds.push_back(seg_node[q]);
+        } else {
+          for (int64_t c = 0; c < nch; ++c) {
+            st.push_back(static_cast<int32_t>(seg_start[q] + c * kVChunk));
+            ln.push_back(static_cast<int32_t>(std::min<int64_t>(kVChunk, d - c * kVChunk)));
+            ds.push_back(static_cast<int32_t>(-(next + c) - 1));
+          }
+          nst.push_back(next);
+          nln.push_back(nch);
+          nnd.push_back(seg_node[q]);
+          next += nch;
+        }
+      }
+      const int l = g.nlev++;
+      g.nchunk[l] = static_cast<int32_t>(st.size());
+      g.npart[l] = static_cast<int32_t>(next);
+      good = dalloc(&g.cstart[l], st.size()) && dalloc(&g.clen[l], st.size()) && dalloc(&g.cdst[l], st.size()) &&
+             hipMemcpy(g.cstart[l], st.data(), 4 * st.size(), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(g.clen[l], ln.data(), 4 * ln.size(), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(g.cdst[l], ds.data(), 4 * ds.size(), hipMemcpyHostToDevice) == hipSuccess;
+      seg_start = std::move(nst);
+      seg_len = std::move(nln);
+      seg_node = std::move(nnd);
+    }
+  }
   if (good) {
     hipLaunchKernelGGL(feat_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, g);
     hipLaunchKernelGGL(inv_size_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, 0, g);
@@ -592,6 +702,11 @@ int sttsv_mpnn_graph_destroy(sttsv_mpnn_graph_t G) {
   for (void* q : {(void*)g.eptr, (void*)g.eidx, (void*)g.nptr, (void*)g.nedge, (void*)g.inv_size, (void*)g.inv_deg,
                   (void*)g.X0})
     (void)hipFree(q);
+  for (int l = 0; l < g.nlev; ++l) {
+    (void)hipFree(g.cstart[l]);
+    (void)hipFree(g.clen[l]);
+    (void)hipFree(g.cdst[l]);
+  }
   delete G;
   return STTSV_OK;
 }
@@ -657,7 +772,13 @@ int sttsv_mpnn_warm_start(sttsv_mpnn_t M, sttsv_mpnn_graph_t G, double* x0) {
   if (M == nullptr || G == nullptr || x0 == nullptr) return STTSV_EINVAL;
   int rc = sttsv::mpnn::forward(M->n, G->g, 0);
   if (rc != STTSV_OK) return rc;
-  hipLaunchKernelGGL(sttsv::mpnn::warm_kernel, dim3(1), dim3(256), 0, 0, (const float*)M->n.s, G->g.n, x0);
+  using namespace sttsv::mpnn;
+  const int nb = std::max(1, std::min(512, (G->g.n + 255) / 256));
+  double* buf = reinterpret_cast<double*>(M->n.part);          // >= 2048 floats = 1024 doubles
+  hipLaunchKernelGGL(warm_max, dim3(nb), dim3(256), 0, 0, (const float*)M->n.s, G->g.n, buf);
+  hipLaunchKernelGGL(warm_exp, dim3(nb), dim3(256), 0, 0, (const float*)M->n.s, G->g.n, (const double*)buf, nb, x0,
+                     buf + 512);
+  hipLaunchKernelGGL(warm_div, dim3(nb), dim3(256), 0, 0, G->g.n, (const double*)(buf + 512), nb, x0);
   return sttsv::mpnn::ok(hipGetLastError());
 }
 
@@ -676,6 +797,8 @@ int sttsv_mpnn_destroy(sttsv_mpnn_t M) {
   }
   (void)hipFree(N.X[1]);
   (void)hipFree(N.X[2]);
+  (void)hipFree(N.vpart[0]);
+  (void)hipFree(N.vpart[1]);
   delete M;
   return STTSV_OK;
 }

@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=256)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the STTSV path is built and measured on a single "
@@ -260,6 +262,17 @@ def main():
     plan_s = time.perf_counter() - t0
     xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
     yd = torch.empty_like(xd)
+
+    if a.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # calibrate the counters taken on the STTSV kernels of the same run
+        src = torch.ones(a.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy of %d MiB done" % a.calib_copy_mib)
+        del src, dst
 
     from paper_2311_08595_amd import _lib as L
     res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist()}

@@ -57,6 +57,12 @@ typedef struct sttsv_plan_s* sttsv_plan_t;
 #define STTSV_FLAG_GENERIC_ONLY 1  /* run every edge of size >= 4 through the generic */
                                    /* (runtime-size) kernel instead of the register-  */
                                    /* resident ones; results are bitwise identical    */
+#define STTSV_FLAG_ONE_STREAM   2  /* launch every edge kernel on the plan's stream.  */
+                                   /* By default the edge launches are spread over   */
+                                   /* the plan's stream and three helper streams of  */
+                                   /* default priority (event fork / join, so work   */
+                                   /* stays ordered on the plan's stream); results   */
+                                   /* are bitwise identical either way               */
 
 /* Options for sttsv_plan.  Pass NULL for all defaults. */
 typedef struct {

@@ -24,6 +24,7 @@ STTSV_MAX_ORDER = 64
 MPNN_NPARAM = 17665
 MPNN_HIDDEN = 64
 FLAG_GENERIC_ONLY = 1
+FLAG_ONE_STREAM = 2
 
 PREC = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"fp64": 0, "fp32_fp64": 1}

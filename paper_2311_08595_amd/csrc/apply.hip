@@ -1,6 +1,9 @@
 // STTSV launch sequence: per-bucket edge kernels (k = 1, 2, 3 and the
 // register-resident k <= 7 kernels), one fused launch per window range for the
 // generic buckets, then the deterministic node reduction.
+#include <algorithm>
+#include <utility>
+
 #include "internal.hpp"
 
 namespace sttsv {
@@ -35,7 +38,7 @@ __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   const double f = frexp(xv, &e2);          // xv = f 2^e2
   double p = 1.0;
   for (int j = 0; j < b.r - 1; ++j) p *= f;
-  c.contrib[b.pos[i]] = ldexp(p, (b.r - 1) * e2);
+  c.contrib[b.slot_off + i] = ldexp(p, (b.r - 1) * e2);
 }
 
 hipError_t launch_k1(const EdgeCall& c, const BucketDesc& b, hipStream_t s) {
@@ -73,6 +76,55 @@ const EdgeTables& edge_tables() {
   return t;
 }
 
+namespace {
+
+// Rough time of an edge launch (s): a fixed launch cost, the incidence bytes
+// at a random-access bandwidth, and the series FMAs at a fraction of the
+// FP64 issue rate.  Only used to balance the stream lanes.
+double edge_cost(int k, int r, int64_t m) {
+  const double W = r - k + 1;
+  double fma = 0.0;
+  if (k == 2) fma = W;
+  else if (k == 3) fma = 3.0 * W + W * (W - 1) / 2;
+  else if (k > 3) fma = (k - 3) * W * (W - 1) + (k + 1) * W;
+  return static_cast<double>(m) * (20.0 * k / 4e12 + 2.0 * fma / 3e13);
+}
+
+// Longest-first greedy assignment of every precision's edge stages to lanes.
+void assign_lanes(Plan& p) {
+  for (int seq = 0; seq < 2; ++seq) {
+    std::vector<Stage>& st = p.stages[seq];
+    std::vector<std::pair<double, size_t>> work;
+    for (size_t t = 0; t < st.size(); ++t) {
+      const Stage& S = st[t];
+      double c = 5e-6;
+      if (S.type == 0) {
+        const Bucket& B = p.buckets[S.index];
+        c += edge_cost(B.k, B.r, B.m);
+      } else if (S.type == 1) {
+        for (int b : p.groups[S.index].buckets) c += edge_cost(p.buckets[b].k, p.buckets[b].r, p.buckets[b].m);
+      } else {
+        continue;
+      }
+      work.emplace_back(c, t);
+    }
+    std::stable_sort(work.begin(), work.end(),
+                     [](const std::pair<double, size_t>& a, const std::pair<double, size_t>& b) {
+                       return a.first > b.first;
+                     });
+    const int nl = std::max(1, std::min<int>(kLanes, static_cast<int>(work.size())));
+    std::vector<double> load(nl, 0.0);
+    for (const auto& w : work) {
+      const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+      st[w.second].lane = l;
+      load[l] += w.first;
+    }
+    p.lanes[seq] = nl;
+  }
+}
+
+}  // namespace
+
 void build_stages(Plan& p) {
   for (int seq = 0; seq < 2; ++seq) {
     std::vector<Stage>& st = p.stages[seq];
@@ -86,6 +138,7 @@ void build_stages(Plan& p) {
       if (p.groups[g].seq == seq) st.push_back(Stage{1, static_cast<int>(g), p.groups[g].f64});
     for (size_t l = 0; l < p.levels.size(); ++l) st.push_back(Stage{2, static_cast<int>(l), true});
   }
+  assign_lanes(p);
 }
 
 int stage_count(const Plan& p, int precision) {
@@ -120,23 +173,45 @@ hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int prec
 
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s) {
-  const int ns = stage_count(p, precision);
-  for (int t = 0; t < ns; ++t) {
-    const hipError_t e = launch_stage(p, t, x, y, precision, done, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const hipError_t e = launch_edges(p, x, precision, done, nullptr, s);
+  return e != hipSuccess ? e : launch_reduction(p, y, done, s);
+}
+
+int init_lanes(Plan& p) {
+  if (hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming) != hipSuccess) return STTSV_EHIP;
+  for (int l = 0; l < kLanes - 1; ++l)
+    if (hipStreamCreateWithFlags(&p.aux[l], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p.ev_join[l], hipEventDisableTiming) != hipSuccess)
+      return STTSV_EHIP;
+  return STTSV_OK;
 }
 
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
                         hipStream_t s) {
   const EdgeCall c{x, p.d_contrib, done, gskip};
-  for (const Stage& S : p.stages[precision == STTSV_PREC_FP32 ? 1 : 0]) {
-    if (S.type == 2) continue;
-    const hipError_t e = launch_stage_call(p, S, c, nullptr, s);
-    if (e != hipSuccess) return e;
+  const int seq = precision == STTSV_PREC_FP32 ? 1 : 0;
+  const int nl = (p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr ? 1 : p.lanes[seq];
+  hipError_t e = hipSuccess;
+  if (nl > 1) {
+    // fork: every helper lane starts after the work already on s
+    if ((e = hipEventRecord(p.ev_fork, s)) != hipSuccess) return e;
+    for (int l = 0; l < nl - 1; ++l)
+      if ((e = hipStreamWaitEvent(p.aux[l], p.ev_fork, 0)) != hipSuccess) return e;
   }
-  return hipSuccess;
+  for (const Stage& S : p.stages[seq]) {
+    if (S.type == 2) continue;
+    const hipStream_t ls = nl > 1 && S.lane > 0 ? p.aux[S.lane - 1] : s;
+    if ((e = launch_stage_call(p, S, c, nullptr, ls)) != hipSuccess) break;
+  }
+  if (nl > 1) {
+    // join (also after a failed launch, so no helper lane is left forked)
+    for (int l = 0; l < nl - 1; ++l) {
+      const hipError_t j = hipEventRecord(p.ev_join[l], p.aux[l]);
+      const hipError_t w = j == hipSuccess ? hipStreamWaitEvent(s, p.ev_join[l], 0) : j;
+      if (e == hipSuccess) e = w;
+    }
+  }
+  return e;
 }
 
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s) {

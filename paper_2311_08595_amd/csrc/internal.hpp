@@ -49,7 +49,7 @@ inline int gen_range_of(int W) {
 // Per-call arguments of the edge kernels.
 struct EdgeCall {
   const double* x;      // input vector
-  double* contrib;      // per-incidence contributions, node-major order
+  double* contrib;      // per-incidence contributions, by member slot (SoA per bucket)
   const int32_t* done;  // whole launch is skipped when *done != 0 (nullable)
   const int32_t* gskip; // per-graph skip flags indexed by BucketDesc::gid (nullable)
 };
@@ -58,7 +58,7 @@ struct EdgeCall {
 // bucket's slot range).
 struct BucketDesc {
   const int32_t* mem;   // member ids, SoA: mem[j*m + i]
-  const int32_t* pos;   // node-major position of each member slot, same layout
+  int64_t slot_off;     // first member slot of the bucket (contributions, SoA like mem)
   const int32_t* gid;   // graph of each edge (batched plans), or null
   void* gstack;         // generic kernel: per-edge global stack (when not in LDS)
   int64_t m;            // edges in the bucket
@@ -95,6 +95,7 @@ struct ReduceLevel {
   int32_t* d_len = nullptr;     // chunk length (0 for an isolated vertex)
   int32_t* d_dst = nullptr;     // >= 0: vertex id (final); < 0: -(partial index)-1
   int64_t in_len = 0;           // length of this level's input array
+  const int32_t* d_gather = nullptr;   // level 0: input index of each term (the slot list)
 };
 
 struct Bucket {
@@ -130,7 +131,13 @@ struct Stage {
   int type;      // 0 = per-bucket edge kernel, 1 = fused generic group, 2 = reduction level
   int index;     // bucket, group or level
   bool f64;      // series type of an edge stage
+  int lane = 0;  // stream lane of an edge stage (0 = the plan's stream)
 };
+
+// Edge launches run on up to kLanes streams: the plan's own and kLanes - 1
+// helpers of default priority, forked from and joined back to the plan's
+// stream with events.
+constexpr int kLanes = 4;
 
 // One hypergraph of a (possibly batched) plan.
 struct GraphInfo {
@@ -163,11 +170,15 @@ struct Plan {
 
   // device buffers
   int32_t* d_mem = nullptr;
-  int32_t* d_pos = nullptr;       // node-major position of every member slot
+  int32_t* d_tslot = nullptr;     // node-major list of member slots (reduction gather)
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
-  double* d_contrib = nullptr;    // node-major contributions
+  double* d_contrib = nullptr;    // contributions by member slot (edge-major SoA)
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
   std::vector<Stage> stages[2];   // launch sequence per precision [fp64, fp32]
+  int lanes[2] = {1, 1};          // stream lanes the edge stages use, per precision
+  hipStream_t aux[kLanes - 1] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kLanes - 1] = {};
   std::vector<ReduceLevel> levels;
   std::vector<double*> d_partials;   // partial arrays for levels >= 1
 
@@ -194,6 +205,7 @@ hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int prec
                         const int32_t* done, hipStream_t s);
 void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t* size, int64_t* count);
 void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
+int init_lanes(Plan& p);      // helper streams and events of the edge lanes
 int build_groups(Plan& p);    // (re)builds the fused generic groups (plan.cpp)
 // The edge launches of one precision (per-graph skip flags, nullable), and
 // the reduction alone: the solver runs both precisions' edge launches then

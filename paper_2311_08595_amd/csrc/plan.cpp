@@ -110,7 +110,7 @@ void free_plan(Plan* p) {
   if (p == nullptr) return;
   free_solver(*p);
   (void)hipFree(p->d_mem);
-  (void)hipFree(p->d_pos);
+  (void)hipFree(p->d_tslot);
   (void)hipFree(p->d_gid);
   (void)hipFree(p->d_contrib);
   for (auto& g : p->groups) {
@@ -127,6 +127,11 @@ void free_plan(Plan* p) {
     (void)hipFree(b.gstack[0]);
     (void)hipFree(b.gstack[1]);
   }
+  for (int l = 0; l < kLanes - 1; ++l) {
+    if (p->aux[l]) (void)hipStreamDestroy(p->aux[l]);
+    if (p->ev_join[l]) (void)hipEventDestroy(p->ev_join[l]);
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   delete p;
 }
 
@@ -499,12 +504,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     return code;
   };
   if ((rc = upload(&P->d_mem, P->mem.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
-  {
-    // node-major position of every member slot: pos[tslot[q]] = q
-    std::vector<int32_t> pos(nnz);
-    for (int64_t q = 0; q < nnz; ++q) pos[P->tslot[q]] = static_cast<int32_t>(q);
-    if ((rc = upload(&P->d_pos, pos.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
-  }
+  if ((rc = upload(&P->d_tslot, P->tslot.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
   for (size_t l = 0; l < hl.size(); ++l) {
@@ -513,6 +513,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     L.in_len = hl[l].in_len;
     P->levels.push_back(L);
     ReduceLevel& D = P->levels.back();
+    if (l == 0) D.d_gather = P->d_tslot;
     if ((rc = upload(&D.d_start, hl[l].start.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
     if ((rc = upload(&D.d_len, hl[l].len.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
     if ((rc = upload(&D.d_dst, hl[l].dst.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
@@ -532,7 +533,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     for (int t = 0; t < 2; ++t) {
       BucketDesc& d = B.desc[t];
       d.mem = P->d_mem + B.slot_off;
-      d.pos = P->d_pos + B.slot_off;
+      d.slot_off = B.slot_off;
       d.gid = P->d_gid != nullptr ? P->d_gid + B.edge_off : nullptr;
       d.gstack = nullptr;
       d.m = B.m;
@@ -554,6 +555,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   }
   if ((rc = build_groups(*P)) != STTSV_OK) return fail(rc);
   build_stages(*P);
+  if (!(P->flags & STTSV_FLAG_ONE_STREAM) && (rc = init_lanes(*P)) != STTSV_OK) return fail(rc);
   if (hipDeviceSynchronize() != hipSuccess) return fail(STTSV_EHIP);
   *out = P;
   return STTSV_OK;

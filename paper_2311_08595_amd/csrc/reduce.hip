@@ -1,7 +1,9 @@
 // Deterministic node-major reduction y_v = sum of v's per-incidence
 // contributions (replaces the AtomicAdd accumulation of Alg. 3 / Alg. 4).
-// The edge kernels store every contribution at its node-major position, so
-// each vertex's terms are contiguous here.
+// The edge kernels store contributions by member slot with coalesced writes;
+// the first level reads each vertex's terms through its slot list (the
+// transpose, in canonical edge order), so the scattered accesses are reads,
+// which cost far less than scattered 8-byte writes.
 //
 // The summation tree of every vertex is fixed by its incidence list alone:
 // the list (canonical edge order) is cut into chunks of kChunk = 32
@@ -20,9 +22,11 @@ constexpr int kGroup = 8;                   // lanes per chunk
 constexpr int kPerLane = kChunk / kGroup;   // terms per lane
 static_assert(kChunk % kGroup == 0, "chunk must split evenly over the group");
 
+template <bool GATHER>
 __global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ start,
                                                     const int32_t* __restrict__ len,
                                                     const int32_t* __restrict__ dst, int64_t nchunks,
+                                                    const int32_t* __restrict__ gather,
                                                     const double* __restrict__ in,
                                                     double* __restrict__ y, double* __restrict__ next,
                                                     const int32_t* done) {
@@ -39,7 +43,7 @@ __global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ 
 #pragma unroll
   for (int q = 0; q < kPerLane; ++q) {
     const int p = j + q * kGroup;
-    idx[q] = p < l ? s + p : -1;
+    idx[q] = p < l ? (GATHER ? gather[s + p] : s + p) : -1;
   }
   double v = 0.0;
 #pragma unroll
@@ -64,8 +68,12 @@ hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y
   if (L.nchunks == 0) return hipSuccess;
   const int64_t threads = L.nchunks * kGroup;
   const dim3 grid(static_cast<unsigned>((threads + 255) / 256));
-  hipLaunchKernelGGL(reduce_level, grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst, L.nchunks, in, y,
-                     next, done);
+  if (L.d_gather != nullptr)
+    hipLaunchKernelGGL(reduce_level<true>, grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst, L.nchunks,
+                       L.d_gather, in, y, next, done);
+  else
+    hipLaunchKernelGGL(reduce_level<false>, grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst, L.nchunks,
+                       nullptr, in, y, next, done);
   return hipGetLastError();
 }
 

@@ -213,6 +213,33 @@ def test_kernel_variants_bitwise_equal(torch_cuda, prec):
         assert a.tobytes() == b.tobytes(), r
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stream_lanes_bitwise_equal(torch_cuda, prec):
+    # edge launches spread over helper streams write disjoint contribution
+    # slots, so y matches the one-stream sequence bit for bit; a plan on a
+    # caller's stream still orders all its work on that stream
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    w = wl.zipf_powerlaw(seed=15, n=50000, m=200000)
+    xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"], flags=_lib.FLAG_ONE_STREAM) as p1, \
+            st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as p2, \
+            st.Plan(w["eptr"], w["eidx"], w["n"], w["r"], stream=side) as p3:
+        a = p1.apply(xd, precision=prec).cpu().numpy()
+        b = p2.apply(xd, precision=prec).cpu().numpy()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            y3 = torch.empty_like(xd)
+            for _ in range(3):
+                p3.apply(xd, y3, precision=prec)
+        side.synchronize()
+        c = y3.cpu().numpy()
+    assert a.tobytes() == b.tobytes()
+    assert a.tobytes() == c.tobytes()
+
+
 def test_autotune_keeps_bits(tmp_path):
     # the tuner only chooses among bitwise-identical variants
     import paper_2311_08595_amd as st

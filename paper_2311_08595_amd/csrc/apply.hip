@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   const double f = frexp(xv, &e2);          // xv = f 2^e2
   double p = 1.0;
   for (int j = 0; j < b.r - 1; ++j) p *= f;
-  c.contrib[b.slot_off + i] = ldexp(p, (b.r - 1) * e2);
+  c.contrib[b.loc[i]] = ldexp(p, (b.r - 1) * e2);
 }
 
 hipError_t launch_k1(const EdgeCall& c, const BucketDesc& b, hipStream_t s) {

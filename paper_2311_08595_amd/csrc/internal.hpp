@@ -23,6 +23,10 @@ constexpr int kMaxW = STTSV_MAX_ORDER;   // windows W = r - k + 1 <= r - 1 for k
 constexpr int kGenBlock = 64;            // threads per block of the generic kernel
 constexpr int kSmallBlock = 256;         // threads per block of the other edge kernels
 constexpr int kChunk = 32;               // reduction chunk length (fixed: part of the format)
+constexpr int kXcd = 8;                  // accelerator dies (XCDs); workgroups go round-robin over them
+constexpr int kRegionTarget = 1 << 17;   // contributions per vertex block (1 MiB of FP64)
+constexpr int kReduceChunksPerBlock = 32;   // level-0 chunks per 256-thread reduction workgroup
+constexpr int32_t kNoDst = INT32_MIN;    // padding chunk of the reduction schedule: no output
 constexpr int kGenRanges = 8;            // window ranges of the fused generic kernels
 constexpr int kGenLo[kGenRanges] = {1, 9, 17, 25, 33, 41, 49, 57};
 constexpr int kGenHi[kGenRanges] = {8, 16, 24, 32, 40, 48, 56, 63};
@@ -49,7 +53,7 @@ inline int gen_range_of(int W) {
 // Per-call arguments of the edge kernels.
 struct EdgeCall {
   const double* x;      // input vector
-  double* contrib;      // per-incidence contributions, by member slot (SoA per bucket)
+  double* contrib;      // per-incidence contributions (one region per vertex block)
   const int32_t* done;  // whole launch is skipped when *done != 0 (nullable)
   const int32_t* gskip; // per-graph skip flags indexed by BucketDesc::gid (nullable)
 };
@@ -58,7 +62,7 @@ struct EdgeCall {
 // bucket's slot range).
 struct BucketDesc {
   const int32_t* mem;   // member ids, SoA: mem[j*m + i]
-  int64_t slot_off;     // first member slot of the bucket (contributions, SoA like mem)
+  const int32_t* loc;   // contribution index of each member slot, SoA like mem
   const int32_t* gid;   // graph of each edge (batched plans), or null
   void* gstack;         // generic kernel: per-edge global stack (when not in LDS)
   int64_t m;            // edges in the bucket
@@ -95,7 +99,7 @@ struct ReduceLevel {
   int32_t* d_len = nullptr;     // chunk length (0 for an isolated vertex)
   int32_t* d_dst = nullptr;     // >= 0: vertex id (final); < 0: -(partial index)-1
   int64_t in_len = 0;           // length of this level's input array
-  const int32_t* d_gather = nullptr;   // level 0: input index of each term (the slot list)
+  const int32_t* d_gather = nullptr;   // level 0: contribution index of each term
 };
 
 struct Bucket {
@@ -104,6 +108,7 @@ struct Bucket {
   int64_t m = 0;
   int64_t edge_off = 0;   // first canonical edge
   int64_t slot_off = 0;   // first member slot
+  int64_t task0 = -1;     // first workgroup of the bucket in its FP64 fused generic launch
   int32_t qexp32 = 0;     // FP32 series scale exponent
   bool fp32_ok = true;    // FP32 series representable for this size
   void* gstack[2] = {nullptr, nullptr};  // generic-kernel global stacks [fp64, fp32]
@@ -170,9 +175,12 @@ struct Plan {
 
   // device buffers
   int32_t* d_mem = nullptr;
-  int32_t* d_tslot = nullptr;     // node-major list of member slots (reduction gather)
+  std::vector<int32_t> vblock;    // vertex block of every vertex
+  std::vector<int64_t> region;    // first contribution index of every block (+ nnz at the end)
+  int32_t* d_loc = nullptr;       // contribution index of every member slot
+  int32_t* d_glist = nullptr;     // contribution index of every node-major incidence
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
-  double* d_contrib = nullptr;    // contributions by member slot (edge-major SoA)
+  double* d_contrib = nullptr;    // contributions, one region per vertex block
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
   std::vector<Stage> stages[2];   // launch sequence per precision [fp64, fp32]
   int lanes[2] = {1, 1};          // stream lanes the edge stages use, per precision
@@ -207,6 +215,7 @@ void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t*
 void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
 int init_lanes(Plan& p);      // helper streams and events of the edge lanes
 int build_groups(Plan& p);    // (re)builds the fused generic groups (plan.cpp)
+int assign_places(Plan& p);   // contribution places for the current kernel choice (plan.cpp)
 // The edge launches of one precision (per-graph skip flags, nullable), and
 // the reduction alone: the solver runs both precisions' edge launches then
 // one reduction per iteration.

@@ -12,7 +12,16 @@
 //  6. member slots in structure-of-arrays form: member j of the i-th edge of
 //     bucket k at slot_off(k) + j m_k + i, slot_off(k) = sum_{k'<k} k' m_k';
 //  7. node-major incidence lists: for each v the slots holding v, in
-//     canonical edge order.
+//     canonical edge order;
+//  8. contribution storage: vertices (in index order) form blocks of about
+//     kRegionTarget incidences; each block owns a contiguous region, split
+//     into one part per die (workgroup w of a launch runs on die w mod 8),
+//     and the incidences that one die's edge workgroups produce for the
+//     block take consecutive places in its part, in (bucket, edge, member)
+//     order.  The edge kernels' stores then advance a few thousand write
+//     fronts, each filled by one die's L2, instead of landing anywhere in
+//     the array, and the reduction of one block gathers from one L2-sized
+//     region.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +34,78 @@
 
 namespace sttsv {
 namespace {
+
+// One level of the reduction schedule (host side).
+struct HostLevel {
+  std::vector<int32_t> start, len, dst;
+  int64_t in_len = 0;
+};
+
+// Launch order of reduction level 0.  Workgroup w takes chunks
+// [kReduceChunksPerBlock w, +kReduceChunksPerBlock) and is dispatched to die
+// w mod kXcd.  Each die receives whole vertex blocks (largest first, to the
+// least-loaded die) and works through them in turn, so the region it gathers
+// from stays in its own L2; a block heavier than half a die's share (a hub,
+// whose terms are contiguous anyway) is dealt over all dies.  Inside a block
+// the chunks go longest first, so the lanes of a wave do similar work.
+// Dies with fewer workgroups are padded with empty chunks (dst = kNoDst).
+HostLevel xcd_schedule(const HostLevel& L, const std::vector<int32_t>& cblock) {
+  constexpr int G = kReduceChunksPerBlock;
+  const int64_t nc = static_cast<int64_t>(L.len.size());
+  int32_t nb = 0;
+  for (int64_t c = 0; c < nc; ++c) nb = std::max(nb, cblock[c] + 1);
+  std::vector<std::vector<int64_t>> bc(nb);
+  for (int64_t c = 0; c < nc; ++c) bc[cblock[c]].push_back(c);
+  int64_t total = 0;
+  for (auto& v : bc) {
+    std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t b) { return L.len[a] > L.len[b]; });
+    total += (static_cast<int64_t>(v.size()) + G - 1) / G;
+  }
+  std::vector<int32_t> order(nb);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return bc[a].size() > bc[b].size(); });
+  const int64_t big = std::max<int64_t>(1, total / (2 * kXcd));
+  std::vector<std::vector<std::pair<int32_t, int64_t>>> queue(kXcd);   // (block, first chunk in block)
+  auto least = [&]() {
+    int x = 0;
+    for (int y = 1; y < kXcd; ++y)
+      if (queue[y].size() < queue[x].size()) x = y;
+    return x;
+  };
+  for (int32_t b : order) {
+    const int64_t ng = (static_cast<int64_t>(bc[b].size()) + G - 1) / G;
+    if (ng > big) {
+      for (int64_t g = 0; g < ng; ++g) queue[least()].emplace_back(b, g * G);
+    } else {
+      const int x = least();
+      for (int64_t g = 0; g < ng; ++g) queue[x].emplace_back(b, g * G);
+    }
+  }
+  size_t rounds = 0;
+  for (const auto& q : queue) rounds = std::max(rounds, q.size());
+  HostLevel R;
+  R.in_len = L.in_len;
+  for (size_t t = 0; t < rounds; ++t)
+    for (int x = 0; x < kXcd; ++x) {
+      int64_t filled = 0;
+      if (t < queue[x].size()) {
+        const auto& v = bc[queue[x][t].first];
+        for (int64_t i = queue[x][t].second; i < std::min<int64_t>(queue[x][t].second + G, v.size()); ++i) {
+          R.start.push_back(L.start[v[i]]);
+          R.len.push_back(L.len[v[i]]);
+          R.dst.push_back(L.dst[v[i]]);
+          ++filled;
+        }
+      }
+      for (; filled < G; ++filled) {
+        R.start.push_back(0);
+        R.len.push_back(0);
+        R.dst.push_back(kNoDst);
+      }
+    }
+  return R;
+}
 
 struct Dsu {
   std::vector<int32_t> p;
@@ -110,7 +191,8 @@ void free_plan(Plan* p) {
   if (p == nullptr) return;
   free_solver(*p);
   (void)hipFree(p->d_mem);
-  (void)hipFree(p->d_tslot);
+  (void)hipFree(p->d_loc);
+  (void)hipFree(p->d_glist);
   (void)hipFree(p->d_gid);
   (void)hipFree(p->d_contrib);
   for (auto& g : p->groups) {
@@ -240,6 +322,7 @@ int build_groups(Plan& P) {
     P.device_bytes -= g.bytes;
   }
   P.groups.clear();
+  for (Bucket& B : P.buckets) B.task0 = -1;
   int rc = STTSV_OK;
   for (int seq = 0; seq < 2; ++seq) {
     for (int rg = 0; rg < kGenRanges; ++rg) {
@@ -269,6 +352,7 @@ int build_groups(Plan& P) {
         std::vector<GenTask> tasks;
         for (size_t q = 0; q < grp.buckets.size(); ++q) {
           Bucket& B = P.buckets[grp.buckets[q]];
+          if (seq == 0 && t == 0) B.task0 = static_cast<int64_t>(tasks.size());
           const int W = B.r - B.k + 1;
           const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, static_cast<int>(tsz));
           BucketDesc& d = B.desc[t];
@@ -300,6 +384,47 @@ int build_groups(Plan& P) {
       }
     }
   }
+  return STTSV_OK;
+}
+
+// Die that runs edge i of bucket B in the FP64 launch sequence.
+static int edge_die(const Bucket& B, int64_t i) {
+  if (B.k == 1 || B.small_kind[0] >= 0) return static_cast<int>((i / kSmallBlock) % kXcd);
+  if (B.task0 >= 0) return static_cast<int>((B.task0 + i / kGenBlock) % kXcd);
+  return 0;
+}
+
+int assign_places(Plan& P) {
+  const int64_t nnz = P.nnz;
+  const int32_t nb = static_cast<int32_t>(P.region.size()) - 1;
+  std::vector<int64_t> cur((size_t)nb * kXcd, 0);
+  for (const Bucket& B : P.buckets)
+    for (int64_t i = 0; i < B.m; ++i) {
+      const int x = edge_die(B, i);
+      for (int j = 0; j < B.k; ++j) cur[(size_t)P.vblock[P.mem[B.slot_off + (int64_t)j * B.m + i]] * kXcd + x]++;
+    }
+  for (int32_t b = 0; b < nb; ++b) {
+    int64_t at = P.region[b];
+    for (int x = 0; x < kXcd; ++x) {
+      const int64_t c = cur[(size_t)b * kXcd + x];
+      cur[(size_t)b * kXcd + x] = at;
+      at += c;
+    }
+  }
+  std::vector<int32_t> loc(nnz);
+  for (const Bucket& B : P.buckets)
+    for (int64_t i = 0; i < B.m; ++i) {
+      const int x = edge_die(B, i);
+      for (int j = 0; j < B.k; ++j) {
+        const int64_t s = B.slot_off + (int64_t)j * B.m + i;
+        loc[s] = static_cast<int32_t>(cur[(size_t)P.vblock[P.mem[s]] * kXcd + x]++);
+      }
+    }
+  std::vector<int32_t> glist(nnz);
+  for (int64_t q = 0; q < nnz; ++q) glist[q] = loc[P.tslot[q]];
+  if (nnz > 0 && (hipMemcpy(P.d_loc, loc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess ||
+                  hipMemcpy(P.d_glist, glist.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess))
+    return STTSV_EHIP;
   return STTSV_OK;
 }
 
@@ -429,11 +554,26 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     for (int32_t v = 0; v < gs[g].n; ++v) deg[(int64_t)P->graphs[g].voff + v] = degs[g][v];
   degs.clear();
 
+  // ---- vertex blocks (layout item 8; places are assigned once the kernels are chosen)
+  std::vector<int32_t>& vblock = P->vblock;
+  vblock.assign(n, 0);
+  {
+    int64_t acc = 0;
+    int32_t b = 0;
+    P->region.assign(1, 0);
+    for (int32_t u = 0; u < n; ++u) {
+      if (acc > 0 && acc + deg[u] > kRegionTarget) {
+        P->region.push_back(P->region.back() + acc);
+        ++b;
+        acc = 0;
+      }
+      vblock[u] = b;
+      acc += deg[u];
+    }
+    P->region.push_back(nnz);
+  }
+
   // ---- reduction schedule
-  struct HostLevel {
-    std::vector<int32_t> start, len, dst;
-    int64_t in_len = 0;
-  };
   std::vector<HostLevel> hl;
   {
     // level 0 input: contributions gathered through tslot; segment of v = [tptr[v], tptr[v+1])
@@ -452,9 +592,11 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       std::vector<int64_t> nstart, nlen;
       std::vector<int32_t> nnode;
       int64_t next_len = 0;
+      std::vector<int32_t> cblock;   // level 0: vertex block of every chunk
       for (size_t q = 0; q < seg_node.size(); ++q) {
         const int64_t d = seg_len[q];
         const int64_t nch = d <= kChunk ? 1 : (d + kChunk - 1) / kChunk;
+        if (first) cblock.insert(cblock.end(), nch, vblock[seg_node[q]]);
         if (nch == 1) {
           L.start.push_back(static_cast<int32_t>(d > 0 ? seg_start[q] : 0));
           L.len.push_back(static_cast<int32_t>(d));
@@ -472,21 +614,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
         }
       }
       if (first) {
-        // longest chunks first so that the lanes of a wave do similar work
-        std::vector<int64_t> o(L.len.size());
-        std::iota(o.begin(), o.end(), 0);
-        std::stable_sort(o.begin(), o.end(), [&](int64_t a, int64_t b) { return L.len[a] > L.len[b]; });
-        HostLevel S;
-        S.in_len = L.in_len;
-        S.start.resize(o.size());
-        S.len.resize(o.size());
-        S.dst.resize(o.size());
-        for (size_t t = 0; t < o.size(); ++t) {
-          S.start[t] = L.start[o[t]];
-          S.len[t] = L.len[o[t]];
-          S.dst[t] = L.dst[o[t]];
-        }
-        L = std::move(S);
+        L = xcd_schedule(L, cblock);
         first = false;
       }
       hl.push_back(std::move(L));
@@ -504,7 +632,8 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     return code;
   };
   if ((rc = upload(&P->d_mem, P->mem.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
-  if ((rc = upload(&P->d_tslot, P->tslot.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload<int32_t>(&P->d_glist, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
   for (size_t l = 0; l < hl.size(); ++l) {
@@ -513,7 +642,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     L.in_len = hl[l].in_len;
     P->levels.push_back(L);
     ReduceLevel& D = P->levels.back();
-    if (l == 0) D.d_gather = P->d_tslot;
+    if (l == 0) D.d_gather = P->d_glist;
     if ((rc = upload(&D.d_start, hl[l].start.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
     if ((rc = upload(&D.d_len, hl[l].len.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
     if ((rc = upload(&D.d_dst, hl[l].dst.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
@@ -533,7 +662,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     for (int t = 0; t < 2; ++t) {
       BucketDesc& d = B.desc[t];
       d.mem = P->d_mem + B.slot_off;
-      d.slot_off = B.slot_off;
+      d.loc = P->d_loc + B.slot_off;
       d.gid = P->d_gid != nullptr ? P->d_gid + B.edge_off : nullptr;
       d.gstack = nullptr;
       d.m = B.m;
@@ -554,6 +683,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     }
   }
   if ((rc = build_groups(*P)) != STTSV_OK) return fail(rc);
+  if ((rc = assign_places(*P)) != STTSV_OK) return fail(rc);
   build_stages(*P);
   if (!(P->flags & STTSV_FLAG_ONE_STREAM) && (rc = init_lanes(*P)) != STTSV_OK) return fail(rc);
   if (hipDeviceSynchronize() != hipSuccess) return fail(STTSV_EHIP);

@@ -1,9 +1,9 @@
 // Deterministic node-major reduction y_v = sum of v's per-incidence
 // contributions (replaces the AtomicAdd accumulation of Alg. 3 / Alg. 4).
-// The edge kernels store contributions by member slot with coalesced writes;
-// the first level reads each vertex's terms through its slot list (the
-// transpose, in canonical edge order), so the scattered accesses are reads,
-// which cost far less than scattered 8-byte writes.
+// Contributions live in one region per vertex block (about 1 MiB each, see
+// the planner); the first level gathers each vertex's terms from its block's
+// region, and its workgroups are ordered so that every die works through
+// its own blocks one at a time, keeping the gathered region in its L2.
 //
 // The summation tree of every vertex is fixed by its incidence list alone:
 // the list (canonical edge order) is cut into chunks of kChunk = 32
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ 
     const int32_t d = dst[c];
     if (d >= 0)
       y[d] = v;
-    else
+    else if (d != kNoDst)
       next[-(int64_t)d - 1] = v;
   }
 }

@@ -161,7 +161,8 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
   }
   if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
   free_solver(p);                 // the captured launch sequence changes
-  const int rc = build_groups(p);
+  int rc = build_groups(p);
+  if (rc == STTSV_OK) rc = assign_places(p);   // the die of an edge follows its kernel
   if (rc != STTSV_OK) return rc;
   build_stages(p);
   if (tuned != nullptr) *tuned = count;

@@ -76,10 +76,11 @@ GEN_HI = [8, 16, 24, 32, 40, 48, 56, 63]
 
 def stage_work(stages, bucket_k, bucket_m, r):
     """Algorithmic FLOPs and HBM bytes of every stage.  Edge stages: series
-    FMAs x 2 and 20 B per incidence; fused generic stages: the same summed over
-    the buckets that no per-bucket stage covers and whose window is in the
-    stage's range; reduction levels: 8 B per term read, 12 B per chunk
-    descriptor, 8 B per result written."""
+    FMAs x 2 and 20 B per incidence (member id, gathered x, contribution);
+    fused generic stages: the same summed over the buckets that no per-bucket
+    stage covers and whose window is in the stage's range; reduction levels:
+    per term the value read (8 B, plus its 4 B gather index at level 0), per
+    chunk its 12 B descriptor and the 8 B result."""
     per_bucket = {s["size"] for s in stages if s["kind"] == 0}
     out = []
     for s in stages:
@@ -96,21 +97,85 @@ def stage_work(stages, bucket_k, bucket_m, r):
                     b += edge_bytes(k) * m
             out.append((f, b, "generic edges W in [%d,%d], %d edges" % (GEN_LO[g], GEN_HI[g], s["count"])))
         else:
-            out.append((0.0, 8.0 * s["in_len"] + 20.0 * s["count"], "reduce level %d, %d chunks" % (s["size"], s["count"])))
+            per_term = 12.0 if s["size"] == 0 else 8.0
+            out.append((0.0, per_term * s["in_len"] + 20.0 * s["count"],
+                        "reduce level %d, %d chunks" % (s["size"], s["count"])))
     return out
 
 
-def roofline_of(stages, work, prec):
+def source_fingerprint():
+    """sha256 over the kernel and planner sources: traffic figures taken from
+    counters apply only while it is unchanged."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2311_08595_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".inc", ".hpp", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sttsv_zipf_n1e6_m5e6_r25_traffic.md")
+
+
+def measured_traffic(kernel, grid):
+    """Calibrated HBM bytes per dispatch of (kernel, grid) from the committed
+    counter summary, or None when there is none for this kernel or the
+    sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fp = None
+    rows = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("source fingerprint:"):
+                fp = line.split(":", 1)[1].strip().strip("`")
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) == 6 and (cells[1].isdigit() or cells[1] == "-"):
+                try:
+                    rows[(cells[0], int(cells[1]) if cells[1] != "-" else None)] = float(cells[5])
+                except ValueError:
+                    pass
+    if fp != source_fingerprint():
+        return None
+    v = rows.get((kernel, grid))
+    if v is None:
+        v = rows.get((kernel, None))
+    return None if v is None else v * 1e6
+
+
+SMALL_KIND = {2: 0, 3: 1, 4: 2, 5: 3, 6: 4, 7: 5}
+
+
+def stage_kernel(s, prec, r):
+    """Kernel name (template form, as the profiler prints it) and grid size
+    of a stage; grid None where one launch per apply has that name."""
+    t = "double" if prec == "fp64" else "float"
+    if s["kind"] == 0 and s["size"] in SMALL_KIND:
+        return "edge_small<%s, %d, %d>" % (t, r - s["size"] + 1, SMALL_KIND[s["size"]]), (s["count"] + 255) // 256 * 256
+    if s["kind"] == 1:
+        return "edge_generic<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
+    if s["kind"] == 2:
+        return ("reduce_level<true>" if s["size"] == 0 else "reduce_level<false>"), s["count"] * 8
+    return None, None
+
+
+def roofline_of(stages, work, prec, r):
     """Dominant stage and its roofline figures."""
     i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
     t = stages[i]["ms"] * 1e-3
     flops, byts, name = work[i]
     peak_f = PEAK_FP64_VALU      # FP64 FMA and non-packed FP32 FMA issue at the same rate
+    kname, grid = stage_kernel(stages[i], prec, r)
+    traffic = measured_traffic(kname, grid) if kname else None
     if flops / peak_f >= byts / PEAK_HBM:
         return stages[i], dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
-                               frac=(flops / t) / peak_f, traffic=None, kernel=name)
+                               frac=(flops / t) / peak_f, traffic=traffic, kernel=name)
     return stages[i], dict(bound="hbm", achieved=byts / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                           frac=(byts / t) / PEAK_HBM, traffic=None, kernel=name)
+                           frac=(byts / t) / PEAK_HBM, traffic=traffic, kernel=name,
+                           algorithmic_bytes=byts)
 
 
 def cpu_baseline(w, sample_edges, seed=0):
@@ -318,10 +383,10 @@ def main():
     bk, bm = res["bucket_k"], res["bucket_m"]
     for prec in ("fp64", "fp32"):
         res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r)
-    best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64")
+    best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64", r)
     roof["avg_kernel_ms"] = best["ms"]
     out["roofline"] = roof
-    best32, roof32 = roofline_of(res["fp32"]["stages"], res["fp32"]["work"], "fp32")
+    best32, roof32 = roofline_of(res["fp32"]["stages"], res["fp32"]["work"], "fp32", r)
     roof32["avg_kernel_ms"] = best32["ms"]
     out["fp32_series"] = {"value": m / (res["fp32"]["ms"] * 1e-3), "ms_per_step": res["fp32"]["ms"],
                           "roofline": roof32}

@@ -63,6 +63,13 @@ typedef struct sttsv_plan_s* sttsv_plan_t;
                                    /* default priority (event fork / join, so work   */
                                    /* stays ordered on the plan's stream); results   */
                                    /* are bitwise identical either way               */
+#define STTSV_FLAG_PREFIX_REUSE 4  /* FP64 edges of size 4..7: one thread takes a run */
+                                   /* of up to 4 consecutive canonical edges with the */
+                                   /* same first two members and computes their      */
+                                   /* shared prefix product phi_0 phi_1 once (the    */
+                                   /* convolution memoisation of Sec. IV-B over the  */
+                                   /* shared prefixes of Sec. III); results are      */
+                                   /* bitwise identical                              */
 
 /* Options for sttsv_plan.  Pass NULL for all defaults. */
 typedef struct {
@@ -317,6 +324,9 @@ int sttsv_mpnn_warm_start(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, double* x0);
                                /*             (INT32_MIN: size runs in FP64), for */
                                /*             the first graph's order r           */
 #define STTSV_Q_BUCKET_R    8  /* int64[nb]  tensor order of each bucket          */
+#define STTSV_Q_BUCKET_RUNS 9  /* int64[nb]  FP64 prefix-reuse runs of each bucket */
+                               /*            (0: the bucket does not reuse; else */
+                               /*            m - runs edges take a shared prefix) */
 
 /* Sizes of the plan: m, n, largest r, nnz, number of buckets, number of
  * graphs, connected flag (all graphs). */

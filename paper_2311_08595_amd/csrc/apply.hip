@@ -151,6 +151,10 @@ static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, 
     const Bucket& B = p.buckets[S.index];
     const BucketDesc& d = B.desc[S.f64 ? 0 : 1];
     if (B.k == 1) return tab.k1(c, d, s);
+    if (S.f64 && B.reuse) {
+      const SmallLaunchFn fr = tab.run64[B.k - 4][d.W];
+      return fr ? fr(c, d, s) : hipErrorInvalidValue;
+    }
     const SmallLaunchFn fn = S.f64 ? tab.small64[B.small_kind[0]][d.W] : tab.small32[B.small_kind[1]][d.W];
     return fn ? fn(c, d, s) : hipErrorInvalidValue;
   }

@@ -5,6 +5,7 @@
 namespace sttsv {
 void fill_edge_part3(EdgeTables& t) {
   fill_range<double, 46, 50>(t.small64);
+  fill_run_range<46, 50>(t.run64);
   fill_range<float, 46, 50>(t.small32);
 }
 }  // namespace sttsv

@@ -27,6 +27,7 @@ constexpr int kXcd = 8;                  // accelerator dies (XCDs); workgroups 
 constexpr int kRegionTarget = 1 << 17;   // contributions per vertex block (1 MiB of FP64)
 constexpr int kReduceChunksPerBlock = 32;   // level-0 chunks per 256-thread reduction workgroup
 constexpr int32_t kNoDst = INT32_MIN;    // padding chunk of the reduction schedule: no output
+constexpr int kRunMax = 4;               // prefix reuse: edges per run (per thread)
 constexpr int kGenRanges = 8;            // window ranges of the fused generic kernels
 constexpr int kGenLo[kGenRanges] = {1, 9, 17, 25, 33, 41, 49, 57};
 constexpr int kGenHi[kGenRanges] = {8, 16, 24, 32, 40, 48, 56, 63};
@@ -69,8 +70,14 @@ struct BucketDesc {
   int32_t k, r, W;      // edge size, tensor order, series window r - k + 1
   int32_t qexp;         // series scale exponent (rho = 2^qexp)
   int32_t lds_stack;    // generic kernel: 1 = stack in LDS
-  int32_t pad;
+  int32_t reuse_emin;   // prefix reuse: smallest exponent of z_0, z_1 with an exact rescale
   double wk;            // w(e)/|beta(e)| (r-1)!
+  // prefix reuse (FP64 register-resident kernels): runs of consecutive edges
+  // with the same first two members, longest first; run_cnt[L] runs of
+  // kRunMax - L edges
+  const int32_t* run_start;
+  int64_t nruns;
+  int32_t run_cnt[4];
 };
 
 // One block of a fused generic launch: 64 consecutive edges of a bucket.
@@ -86,6 +93,7 @@ using GenLaunchFn = hipError_t (*)(const EdgeCall&, const BucketDesc* bks, const
 struct EdgeTables {
   SmallLaunchFn small64[SK_COUNT][kMaxW + 1];
   SmallLaunchFn small32[SK_COUNT][kMaxW + 1];
+  SmallLaunchFn run64[4][kMaxW + 1];     // prefix-reuse variants, k = 4..7, FP64
   GenLaunchFn gen64[kGenRanges];
   GenLaunchFn gen32[kGenRanges];
   SmallLaunchFn k1;
@@ -115,6 +123,10 @@ struct Bucket {
   BucketDesc desc[2];     // [fp64 series, fp32 series]
   int small_kind[2] = {-1, -1};          // SmallKind, or -1: generic / k = 1
   int lds_pref[2] = {-1, -1};            // generic stack placement: -1 auto, 0 global, 1 LDS
+  bool reuse = false;                    // FP64 register-resident kernel with prefix reuse
+  int reuse_pref = -1;                   // tuner choice: -1 flag decides, 0 off, 1 on
+  std::vector<int32_t> runs;             // host copy of the run starts (longest first)
+  int32_t* d_runs = nullptr;
 };
 
 // A fused generic launch: all generic buckets of one precision whose window
@@ -216,6 +228,7 @@ void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
 int init_lanes(Plan& p);      // helper streams and events of the edge lanes
 int build_groups(Plan& p);    // (re)builds the fused generic groups (plan.cpp)
 int assign_places(Plan& p);   // contribution places for the current kernel choice (plan.cpp)
+int set_reuse(Plan& p, Bucket& b, bool by_flag);   // prefix-reuse runs of a bucket (plan.cpp)
 // The edge launches of one precision (per-graph skip flags, nullable), and
 // the reduction alone: the solver runs both precisions' edge launches then
 // one reduction per iteration.

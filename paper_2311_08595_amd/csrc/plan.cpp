@@ -208,6 +208,7 @@ void free_plan(Plan* p) {
   for (auto& b : p->buckets) {
     (void)hipFree(b.gstack[0]);
     (void)hipFree(b.gstack[1]);
+    (void)hipFree(b.d_runs);
   }
   for (int l = 0; l < kLanes - 1; ++l) {
     if (p->aux[l]) (void)hipStreamDestroy(p->aux[l]);
@@ -387,22 +388,86 @@ int build_groups(Plan& P) {
   return STTSV_OK;
 }
 
-// Die that runs edge i of bucket B in the FP64 launch sequence.
-static int edge_die(const Bucket& B, int64_t i) {
-  if (B.k == 1 || B.small_kind[0] >= 0) return static_cast<int>((i / kSmallBlock) % kXcd);
-  if (B.task0 >= 0) return static_cast<int>((B.task0 + i / kGenBlock) % kXcd);
-  return 0;
+// Smallest binary exponent of min(z_0, z_1) (both shifts) for which every
+// value of the FP64 product phi(z_0 t) phi(z_1 t) truncated to W terms stays
+// normal with a margin of 2^16: z^(W-1) / W! >= 2^(-1006).
+static int reuse_emin(int W) {
+  if (W < 2) return INT32_MIN / 2;
+  double lf = 0.0;   // log2(W!)
+  for (int q = 2; q <= W; ++q) lf += std::log2(static_cast<double>(q));
+  return static_cast<int>(std::ceil((-1006.0 + lf) / (W - 1)));
+}
+
+// Prefix reuse for one bucket: runs of at most kRunMax consecutive canonical
+// edges whose first two members agree (hence also their graph), longest
+// first.  Only FP64 register-resident buckets take it.
+int set_reuse(Plan& P, Bucket& B, bool by_flag) {
+  const bool want = B.reuse_pref >= 0 ? B.reuse_pref == 1 : by_flag;
+  const bool ok = B.small_kind[0] >= SK_R4 && B.small_kind[0] <= SK_R7 &&
+                  edge_tables().run64[B.k - 4][B.r - B.k + 1] != nullptr;
+  B.reuse = want && ok;
+  BucketDesc& d = B.desc[0];
+  if (!B.reuse) {
+    d.run_start = nullptr;
+    d.nruns = 0;
+    return STTSV_OK;
+  }
+  if (B.d_runs == nullptr) {
+    std::vector<std::vector<int32_t>> by_len(kRunMax + 1);
+    const int32_t* m0 = P.mem.data() + B.slot_off;
+    const int32_t* m1 = m0 + B.m;
+    for (int64_t i = 0; i < B.m;) {
+      int64_t j = i + 1;
+      while (j < B.m && j - i < kRunMax && m0[j] == m0[i] && m1[j] == m1[i]) ++j;
+      by_len[j - i].push_back(static_cast<int32_t>(i));
+      i = j;
+    }
+    B.runs.clear();
+    for (int L = kRunMax; L >= 1; --L) {
+      d.run_cnt[kRunMax - L] = static_cast<int32_t>(by_len[L].size());
+      B.runs.insert(B.runs.end(), by_len[L].begin(), by_len[L].end());
+    }
+    int rc = upload(&B.d_runs, B.runs.data(), B.runs.size(), &P.device_bytes);
+    if (rc != STTSV_OK) return rc;
+  }
+  d.run_start = B.d_runs;
+  d.nruns = static_cast<int64_t>(B.runs.size());
+  return STTSV_OK;
+}
+
+// Die of every edge of bucket B in the FP64 launch sequence (workgroup w of
+// a launch runs on die w mod kXcd).
+static void edge_dies(const Bucket& B, std::vector<uint8_t>& die) {
+  die.assign(B.m, 0);
+  if (B.reuse) {
+    int64_t t = 0;
+    for (int q = 0; q < kRunMax; ++q)
+      for (int32_t c = 0; c < B.desc[0].run_cnt[q]; ++c, ++t)
+        for (int u = 0; u < kRunMax - q; ++u)
+          die[B.runs[t] + u] = static_cast<uint8_t>((t / kSmallBlock) % kXcd);
+    return;
+  }
+  for (int64_t i = 0; i < B.m; ++i) {
+    if (B.k == 1 || B.small_kind[0] >= 0)
+      die[i] = static_cast<uint8_t>((i / kSmallBlock) % kXcd);
+    else if (B.task0 >= 0)
+      die[i] = static_cast<uint8_t>((B.task0 + i / kGenBlock) % kXcd);
+  }
 }
 
 int assign_places(Plan& P) {
   const int64_t nnz = P.nnz;
   const int32_t nb = static_cast<int32_t>(P.region.size()) - 1;
   std::vector<int64_t> cur((size_t)nb * kXcd, 0);
-  for (const Bucket& B : P.buckets)
+  std::vector<std::vector<uint8_t>> dies(P.buckets.size());
+  for (size_t bi = 0; bi < P.buckets.size(); ++bi) edge_dies(P.buckets[bi], dies[bi]);
+  for (size_t bi = 0; bi < P.buckets.size(); ++bi) {
+    const Bucket& B = P.buckets[bi];
     for (int64_t i = 0; i < B.m; ++i) {
-      const int x = edge_die(B, i);
+      const int x = dies[bi][i];
       for (int j = 0; j < B.k; ++j) cur[(size_t)P.vblock[P.mem[B.slot_off + (int64_t)j * B.m + i]] * kXcd + x]++;
     }
+  }
   for (int32_t b = 0; b < nb; ++b) {
     int64_t at = P.region[b];
     for (int x = 0; x < kXcd; ++x) {
@@ -412,14 +477,16 @@ int assign_places(Plan& P) {
     }
   }
   std::vector<int32_t> loc(nnz);
-  for (const Bucket& B : P.buckets)
+  for (size_t bi = 0; bi < P.buckets.size(); ++bi) {
+    const Bucket& B = P.buckets[bi];
     for (int64_t i = 0; i < B.m; ++i) {
-      const int x = edge_die(B, i);
+      const int x = dies[bi][i];
       for (int j = 0; j < B.k; ++j) {
         const int64_t s = B.slot_off + (int64_t)j * B.m + i;
         loc[s] = static_cast<int32_t>(cur[(size_t)P.vblock[P.mem[s]] * kXcd + x]++);
       }
     }
+  }
   std::vector<int32_t> glist(nnz);
   for (int64_t q = 0; q < nnz; ++q) glist[q] = loc[P.tslot[q]];
   if (nnz > 0 && (hipMemcpy(P.d_loc, loc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess ||
@@ -671,8 +738,11 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       d.W = W;
       d.qexp = t == 1 ? B.qexp32 : 0;
       d.lds_stack = 1;
-      d.pad = 0;
+      d.reuse_emin = reuse_emin(W);
       d.wk = wtab[r][B.k];
+      d.run_start = nullptr;
+      d.nruns = 0;
+      for (int q = 0; q < kRunMax; ++q) d.run_cnt[q] = 0;
       const auto& small = t == 0 ? tab.small64 : tab.small32;
       int kind = -1;
       if (B.k == 2) kind = SK_K2;
@@ -682,6 +752,8 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       B.small_kind[t] = kind;
     }
   }
+  for (Bucket& B : P->buckets)
+    if ((rc = set_reuse(*P, B, (P->flags & STTSV_FLAG_PREFIX_REUSE) != 0)) != STTSV_OK) return fail(rc);
   if ((rc = build_groups(*P)) != STTSV_OK) return fail(rc);
   if ((rc = assign_places(*P)) != STTSV_OK) return fail(rc);
   build_stages(*P);

@@ -1,7 +1,8 @@
 // Autotuner: picks, per size bucket and series type, among kernel variants
 // that compute bitwise-identical contributions (so tuning never changes y):
 //   * 4 <= k <= 7: register-resident kernel vs the generic kernel;
-//   * generic buckets: suffix stack in LDS vs in global memory.
+//   * generic buckets: suffix stack in LDS vs in global memory;
+//   * FP64 register-resident buckets: with or without prefix reuse.
 // Each candidate is launched alone on the plan's stream with the caller's x
 // and timed with hipEvents (median of reps); the choices are kept in the plan
 // and in a cache keyed by (series type, r, k, round(log2 m)), which can be
@@ -24,6 +25,7 @@ namespace {
 struct Choice {
   int use_kr;   // -1 not applicable, 0 generic, 1 register-resident
   int lds;      // -1 not applicable, 0 global stack, 1 LDS stack
+  int reuse;    // -1 not applicable, 0 off, 1 prefix reuse
 };
 
 std::mutex g_mu;
@@ -41,9 +43,9 @@ void load_cache(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (f == nullptr) return;
   char key[96];
-  int a = 0, b = 0;
+  int a = 0, b = 0, c = 0;
   std::lock_guard<std::mutex> lk(g_mu);
-  while (std::fscanf(f, "%95s %d %d", key, &a, &b) == 3) g_cache[key] = Choice{a, b};
+  while (std::fscanf(f, "%95s %d %d %d", key, &a, &b, &c) == 4) g_cache[key] = Choice{a, b, c};
   std::fclose(f);
 }
 
@@ -51,7 +53,7 @@ void append_cache(const char* path, const std::string& key, const Choice& c) {
   if (path == nullptr) return;
   FILE* f = std::fopen(path, "a");
   if (f == nullptr) return;
-  std::fprintf(f, "%s %d %d\n", key.c_str(), c.use_kr, c.lds);
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), c.use_kr, c.lds, c.reuse);
   std::fclose(f);
 }
 
@@ -127,7 +129,7 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
     for (int t = 0; t < 2; ++t) {
       if (t == 1 && !B.fp32_ok) continue;
       const std::string key = key_of(t, B);
-      Choice ch{-1, -1};
+      Choice ch{-1, -1, -1};
       bool cached = false;
       {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -147,7 +149,23 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
         ch.use_kr = -1;
         if (kr != nullptr) {
           const BucketDesc d = B.desc[t];
-          const float t_kr = time_median([&] { return kr(c, d, p.stream); }, reps, p.stream);
+          float t_kr = time_median([&] { return kr(c, d, p.stream); }, reps, p.stream);
+          const SmallLaunchFn fr = t == 0 ? tab.run64[B.k - 4][W] : nullptr;
+          if (fr != nullptr) {
+            const int saved_kind = B.small_kind[0], saved_pref = B.reuse_pref;
+            B.small_kind[0] = SK_R4 + (B.k - 4);
+            B.reuse_pref = 1;
+            int rc = set_reuse(p, B, false);
+            float t_run = 1e30f;
+            if (rc == STTSV_OK && B.reuse) {
+              const BucketDesc dr = B.desc[0];
+              t_run = time_median([&] { return fr(c, dr, p.stream); }, reps, p.stream);
+            }
+            B.small_kind[0] = saved_kind;
+            B.reuse_pref = saved_pref;
+            ch.reuse = t_run < t_kr ? 1 : 0;
+            t_kr = std::min(t_kr, t_run);
+          }
           ch.use_kr = t_kr <= g_best ? 1 : 0;
         }
         std::lock_guard<std::mutex> lk(g_mu);
@@ -156,12 +174,16 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
       }
       if (kr != nullptr && ch.use_kr >= 0) B.small_kind[t] = ch.use_kr == 1 ? SK_R4 + (B.k - 4) : -1;
       if (ch.lds >= 0) B.lds_pref[t] = ch.lds;
+      if (t == 0 && ch.reuse >= 0) B.reuse_pref = ch.reuse;
       ++count;
     }
   }
   if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
   free_solver(p);                 // the captured launch sequence changes
-  int rc = build_groups(p);
+  int rc = STTSV_OK;
+  for (Bucket& B : p.buckets)
+    if (rc == STTSV_OK) rc = set_reuse(p, B, (p.flags & STTSV_FLAG_PREFIX_REUSE) != 0);
+  if (rc == STTSV_OK) rc = build_groups(p);
   if (rc == STTSV_OK) rc = assign_places(p);   // the die of an edge follows its kernel
   if (rc != STTSV_OK) return rc;
   build_stages(p);

@@ -25,6 +25,21 @@ def test_header_lists_every_export():
     assert _declared() == sorted(_lib.EXPORTS)
 
 
+def test_header_constants_match_binding():
+    # every STTSV_* integer macro of the header has the same value in the binding
+    src = open(HEADER).read()
+    macros = dict((k, int(v)) for k, v in re.findall(r"^#define\s+STTSV_(\w+)\s+(-?\d+)\b", src, flags=re.M))
+    checked = 0
+    for name, value in macros.items():
+        for attr in (name, "STTSV_" + name):
+            if hasattr(_lib, attr):
+                assert getattr(_lib, attr) == value, name
+                checked += 1
+                break
+    assert macros["FLAG_PREFIX_REUSE"] == _lib.FLAG_PREFIX_REUSE
+    assert checked >= 10
+
+
 def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in _declared():

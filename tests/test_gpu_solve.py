@@ -50,17 +50,18 @@ def test_per_iterate_parity(graph, use_graph):
 
 @pytest.mark.parametrize("schedule", ["fp64", "fp32_fp64"])
 def test_stream_lanes_solve_bitwise(graph, schedule):
-    # the captured iteration with edge launches forked over helper streams
-    # gives the same iterates as the one-stream sequence
+    # the captured iteration with edge launches forked over helper streams,
+    # and with FP64 prefix reuse, gives the same iterates as the one-stream
+    # sequence
     import paper_2311_08595_amd as st
     from paper_2311_08595_amd import _lib
     eptr, eidx, n, r = graph
     out = []
-    for flags in (0, _lib.FLAG_ONE_STREAM):
+    for flags in (0, _lib.FLAG_ONE_STREAM, _lib.FLAG_PREFIX_REUSE):
         with st.Plan(eptr, eidx, n, r, flags=flags) as plan:
             x, info = plan.solve(tol=1e-10, schedule=schedule)
             out.append((x.cpu().numpy().tobytes(), info["iterations"], info["iters_fp32"]))
-    assert out[0] == out[1]
+    assert out[0] == out[1] == out[2]
 
 
 def test_converged_solution(graph):

@@ -240,6 +240,62 @@ def test_stream_lanes_bitwise_equal(torch_cuda, prec):
     assert a.tobytes() == c.tobytes()
 
 
+def _reuse_runs_ref(plan):
+    # runs of consecutive canonical edges with equal first two members, at
+    # most 4 long, recomputed on the host from the plan's slot layout
+    from paper_2311_08595_amd import _lib
+    ks, ms = plan.query(_lib.Q_BUCKET_K), plan.query(_lib.Q_BUCKET_M)
+    mem = plan.query(_lib.Q_MEM)
+    out, off = [], 0
+    for k, m in zip(ks, ms):
+        m0, m1 = mem[off:off + m], mem[off + m:off + 2 * m] if k > 1 else None
+        runs = 0
+        i = 0
+        while i < m and k >= 4:
+            j = i + 1
+            while j < m and j - i < 4 and m0[j] == m0[i] and m1[j] == m1[i]:
+                j += 1
+            runs += 1
+            i = j
+        out.append(runs)
+        off += k * m
+    return np.array(out)
+
+
+def test_prefix_reuse_bitwise_equal(torch_cuda):
+    # runs of edges with the same first two members share phi_0 phi_1 (FP64);
+    # the shared product is rescaled exactly or recomputed, so y agrees bit for
+    # bit with the plain kernels, also where tiny or negative x force the
+    # recomputation
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    w = wl.zipf_powerlaw(seed=16, n=20000, m=100000)
+    rng = np.random.default_rng(5)
+    x = w["x"]
+    xs = [x, x * np.where(rng.random(w["n"]) < 0.1, 1e-250, 1.0), x * np.where(rng.random(w["n"]) < 0.2, -1.0, 1.0)]
+    with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as p1, \
+            st.Plan(w["eptr"], w["eidx"], w["n"], w["r"], flags=_lib.FLAG_PREFIX_REUSE) as p2:
+        runs = p2.query(_lib.Q_BUCKET_RUNS)
+        ks, ms = p2.query(_lib.Q_BUCKET_K), p2.query(_lib.Q_BUCKET_M)
+        ref = _reuse_runs_ref(p2)
+        on = runs > 0
+        assert on.any() and np.all((ks[on] >= 4) & (ks[on] <= 7))
+        assert np.array_equal(runs[on], ref[on])
+        assert np.sum(ms[on] - runs[on]) > 0.3 * np.sum(ms[on])      # Zipf hubs: most edges share
+        assert np.all(p1.query(_lib.Q_BUCKET_RUNS) == 0)
+        for xv in xs:
+            xd = torch.tensor(xv, dtype=torch.float64, device="cuda")
+            for prec in ("fp64", "fp32"):
+                a = p1.apply(xd, precision=prec).cpu().numpy()
+                b = p2.apply(xd, precision=prec).cpu().numpy()
+                assert a.tobytes() == b.tobytes(), prec
+        ref_y = sr.sttsv(w["eptr"], w["eidx"], w["n"], w["r"], x)
+        xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+        y = p2.apply(xd).cpu().numpy()
+        assert _relerr(y, ref_y) <= TOL["fp64"]
+
+
 def test_autotune_keeps_bits(tmp_path):
     # the tuner only chooses among bitwise-identical variants
     import paper_2311_08595_amd as st

@@ -395,6 +395,35 @@ def main():
     out["plan_s"] = plan_s
     plan.close()
 
+    # prefix reuse (FP64, sizes 4..7): a plan with the flag; per-bucket share
+    # of edges that take the shared product phi_0 phi_1 from their run, the
+    # series FMAs that saves, and the time it takes
+    log("[bench] prefix reuse")
+    with st.Plan(w["eptr"], w["eidx"], n, r, flags=L.FLAG_PREFIX_REUSE) as pr:
+        runs = pr.query(L.Q_BUCKET_RUNS)
+        for _ in range(a.warmup):
+            pr.apply(xd, yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            pr.apply(xd, yd)
+        torch.cuda.synchronize()
+        dt_r = (time.perf_counter() - t0) / a.steps
+    total_fma = sum(edge_fma(k, r) * m for k, m in zip(bk, bm))
+    rows, share, saved = [], 0, 0.0
+    for k, m, nr in zip(bk, bm, runs.tolist()):
+        if nr > 0:
+            W = r - k + 1
+            rows.append({"k": k, "edges": m, "runs": nr, "edges_sharing": m - nr})
+            share += m - nr
+            saved += (m - nr) * W * (W - 1) / 2
+    reuse_m = sum(x["edges"] for x in rows)
+    out["prefix_reuse"] = {"buckets": rows, "share_fraction": share / max(reuse_m, 1),
+                           "fma_saved_fraction_of_all_edges": saved / total_fma,
+                           "ms_per_step": dt_r * 1e3, "time_vs_plain": dt_r / (res["fp64"]["ms"] * 1e-3)}
+    log("[bench]   reuse: %.1f%% of size-4..7 edges share, %.1f%% of series FMAs saved, %.3f ms (plain %.3f ms)"
+        % (100 * share / max(reuse_m, 1), 100 * saved / total_fma, dt_r * 1e3, res["fp64"]["ms"]))
+
     if not a.no_solve:
         log("[bench] largest component + solves")
         e2, i2, n2, _ = wl.largest_component(w["eptr"], w["eidx"], n)

@@ -329,13 +329,15 @@ int sttsv_mpnn_warm_start(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, double* x0);
                                /*            m - runs edges take a shared prefix) */
 
 /* Sizes of the plan: m, n, largest r, nnz, number of buckets, number of
- * graphs, connected flag (all graphs). */
+ * graphs, connected flag (all graphs), and the number of streams the FP64
+ * edge launches are spread over (1 with STTSV_FLAG_ONE_STREAM, and for plans
+ * whose estimated edge work is too small to gain from the overlap). */
 typedef struct {
     int64_t m, nnz;
     int32_t n, r, nbuckets, connected;
     int64_t device_bytes;  /* device memory held by the plan                     */
     int32_t graphs;
-    int32_t reserved;
+    int32_t lanes;
 } sttsv_plan_info;
 
 int sttsv_plan_get_info(sttsv_plan_t plan, sttsv_plan_info* info);

@@ -148,7 +148,8 @@ class Plan:
         pi = _lib.PlanInfo()
         _lib.check(self._lib.sttsv_plan_get_info(self._h, ctypes.byref(pi)))
         return dict(m=pi.m, nnz=pi.nnz, n=pi.n, r=pi.r, nbuckets=pi.nbuckets,
-                    connected=bool(pi.connected), device_bytes=pi.device_bytes, graphs=pi.graphs)
+                    connected=bool(pi.connected), device_bytes=pi.device_bytes, graphs=pi.graphs,
+                    lanes=pi.lanes)
 
     def query(self, what):
         inf = self.info()

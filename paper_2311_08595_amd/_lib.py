@@ -63,7 +63,7 @@ class SolveInfo(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n", ctypes.c_int32),
                 ("r", ctypes.c_int32), ("nbuckets", ctypes.c_int32), ("connected", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64), ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("graphs", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
 class GraphDesc(ctypes.Structure):

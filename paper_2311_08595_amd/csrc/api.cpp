@@ -173,7 +173,7 @@ int sttsv_plan_get_info(sttsv_plan_t plan, sttsv_plan_info* info) {
   info->connected = p.connected ? 1 : 0;
   info->device_bytes = p.device_bytes;
   info->graphs = static_cast<int32_t>(p.graphs.size());
-  info->reserved = 0;
+  info->lanes = (p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr ? 1 : p.lanes[0];
   return STTSV_OK;
 }
 

@@ -90,6 +90,10 @@ double edge_cost(int k, int r, int64_t m) {
   return static_cast<double>(m) * (20.0 * k / 4e12 + 2.0 * fma / 3e13);
 }
 
+// Estimated edge work (s, launch costs excluded) below which a plan keeps
+// all edge launches on its own stream.
+constexpr double kLaneMinWork = 20e-6;
+
 // Longest-first greedy assignment of every precision's edge stages to lanes.
 void assign_lanes(Plan& p) {
   for (int seq = 0; seq < 2; ++seq) {
@@ -112,7 +116,10 @@ void assign_lanes(Plan& p) {
                      [](const std::pair<double, size_t>& a, const std::pair<double, size_t>& b) {
                        return a.first > b.first;
                      });
-    const int nl = std::max(1, std::min<int>(kLanes, static_cast<int>(work.size())));
+    // small plans: the fork / join costs more than the overlap can win
+    double total = 0.0;
+    for (const auto& w : work) total += w.first - 5e-6;
+    const int nl = total < kLaneMinWork ? 1 : std::max(1, std::min<int>(kLanes, static_cast<int>(work.size())));
     std::vector<double> load(nl, 0.0);
     for (const auto& w : work) {
       const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());

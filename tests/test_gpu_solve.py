@@ -48,17 +48,25 @@ def test_per_iterate_parity(graph, use_graph):
             assert abs(info["criterion"] - ref["crits"][t - 1]) <= 1e-9 * ref["crits"][t - 1]
 
 
+@pytest.fixture(scope="module")
+def big_graph():
+    w = wl.zipf_powerlaw(seed=22, n=200000, m=1000000)
+    eptr, eidx, n, _ = wl.largest_component(w["eptr"], w["eidx"], w["n"])
+    return eptr, eidx, n, w["r"]
+
+
 @pytest.mark.parametrize("schedule", ["fp64", "fp32_fp64"])
-def test_stream_lanes_solve_bitwise(graph, schedule):
+def test_stream_lanes_solve_bitwise(big_graph, schedule):
     # the captured iteration with edge launches forked over helper streams,
     # and with FP64 prefix reuse, gives the same iterates as the one-stream
     # sequence
     import paper_2311_08595_amd as st
     from paper_2311_08595_amd import _lib
-    eptr, eidx, n, r = graph
+    eptr, eidx, n, r = big_graph
     out = []
     for flags in (0, _lib.FLAG_ONE_STREAM, _lib.FLAG_PREFIX_REUSE):
         with st.Plan(eptr, eidx, n, r, flags=flags) as plan:
+            assert plan.info()["lanes"] == (1 if flags == _lib.FLAG_ONE_STREAM else 4)
             x, info = plan.solve(tol=1e-10, schedule=schedule)
             out.append((x.cpu().numpy().tobytes(), info["iterations"], info["iters_fp32"]))
     assert out[0] == out[1] == out[2]

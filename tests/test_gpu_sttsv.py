@@ -221,12 +221,13 @@ def test_stream_lanes_bitwise_equal(torch_cuda, prec):
     import paper_2311_08595_amd as st
     from paper_2311_08595_amd import _lib
     torch = torch_cuda
-    w = wl.zipf_powerlaw(seed=15, n=50000, m=200000)
+    w = wl.zipf_powerlaw(seed=15, n=200000, m=1000000)
     xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
     side = torch.cuda.Stream()
     with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"], flags=_lib.FLAG_ONE_STREAM) as p1, \
             st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as p2, \
             st.Plan(w["eptr"], w["eidx"], w["n"], w["r"], stream=side) as p3:
+        assert p1.info()["lanes"] == 1 and p2.info()["lanes"] > 1 and p3.info()["lanes"] > 1
         a = p1.apply(xd, precision=prec).cpu().numpy()
         b = p2.apply(xd, precision=prec).cpu().numpy()
         side.wait_stream(torch.cuda.current_stream())

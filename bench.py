@@ -78,9 +78,10 @@ def stage_work(stages, bucket_k, bucket_m, r):
     """Algorithmic FLOPs and HBM bytes of every stage.  Edge stages: series
     FMAs x 2 and 20 B per incidence (member id, gathered x, contribution);
     fused generic stages: the same summed over the buckets that no per-bucket
-    stage covers and whose window is in the stage's range; reduction levels:
-    per term the value read (8 B, plus its 4 B gather index at level 0), per
-    chunk its 12 B descriptor and the 8 B result."""
+    stage covers and whose window is in the stage's range; the copy of x into
+    degree-rank order: 4 B index + 8 B read + 8 B written per vertex;
+    reduction levels: per term the value read (8 B, plus its 4 B gather index
+    at level 0), per chunk its 12 B descriptor and the 8 B result."""
     per_bucket = {s["size"] for s in stages if s["kind"] == 0}
     out = []
     for s in stages:
@@ -96,6 +97,8 @@ def stage_work(stages, bucket_k, bucket_m, r):
                     f += 2.0 * edge_fma(k, r) * m
                     b += edge_bytes(k) * m
             out.append((f, b, "generic edges W in [%d,%d], %d edges" % (GEN_LO[g], GEN_HI[g], s["count"])))
+        elif s["kind"] == 3:
+            out.append((0.0, 20.0 * s["count"], "x into degree-rank order, n=%d" % s["count"]))
         else:
             per_term = 12.0 if s["size"] == 0 else 8.0
             out.append((0.0, per_term * s["in_len"] + 20.0 * s["count"],
@@ -159,6 +162,8 @@ def stage_kernel(s, prec, r):
         return "edge_generic<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
     if s["kind"] == 2:
         return ("reduce_level<true>" if s["size"] == 0 else "reduce_level<false>"), s["count"] * 8
+    if s["kind"] == 3:
+        return "permute_x", (s["count"] + 255) // 256 * 256
     return None, None
 
 

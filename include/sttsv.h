@@ -124,7 +124,9 @@ int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t prec
  * sttsv_apply_timed -- sttsv_apply_prec, with every stage timed by a pair of
  * hipEvents recorded on the plan's stream (for measurement tools).
  *
- * Stage s is one of: the edge-kernel launch of one size bucket
+ * Stage s is one of: the copy of x into degree-rank order that the edge
+ * kernels gather from (kinds[s] = 3, sizes[s] = 0, counts[s] = n); the
+ * edge-kernel launch of one size bucket
  * (kinds[s] = 0, sizes[s] = edge size k, counts[s] = edges in the bucket);
  * a fused launch of the generic kernel over several buckets (kinds[s] = 1,
  * sizes[s] = window-range index, counts[s] = edges covered); one level of

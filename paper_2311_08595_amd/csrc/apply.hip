@@ -41,6 +41,14 @@ __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   c.contrib[b.loc[i]] = ldexp(p, (b.r - 1) * e2);
 }
 
+// x into degree-rank order: xr[p] = x[rid[p]].
+__global__ void __launch_bounds__(256) permute_x(const double* __restrict__ x, const int32_t* __restrict__ rid,
+                                                 int64_t n, double* __restrict__ xr, const int32_t* done) {
+  if (done != nullptr && *done) return;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < n) xr[p] = x[rid[p]];
+}
+
 hipError_t launch_k1(const EdgeCall& c, const BucketDesc& b, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>((b.m + 255) / 256));
   hipLaunchKernelGGL(edge_k1, grid, dim3(256), 0, s, c, b);
@@ -87,7 +95,7 @@ double edge_cost(int k, int r, int64_t m) {
   if (k == 2) fma = W;
   else if (k == 3) fma = 3.0 * W + W * (W - 1) / 2;
   else if (k > 3) fma = (k - 3) * W * (W - 1) + (k + 1) * W;
-  return static_cast<double>(m) * (20.0 * k / 4e12 + 2.0 * fma / 3e13);
+  return static_cast<double>(m) * (20.0 * k / 3.2e12 + 2.0 * fma / 3e13);
 }
 
 // Estimated edge work (s, launch costs excluded) below which a plan keeps
@@ -106,7 +114,8 @@ void assign_lanes(Plan& p) {
         const Bucket& B = p.buckets[S.index];
         c += edge_cost(B.k, B.r, B.m);
       } else if (S.type == 1) {
-        for (int b : p.groups[S.index].buckets) c += edge_cost(p.buckets[b].k, p.buckets[b].r, p.buckets[b].m);
+        // the runtime-k kernel runs at about half the FMA rate of the others
+        for (int b : p.groups[S.index].buckets) c += 2.0 * edge_cost(p.buckets[b].k, p.buckets[b].r, p.buckets[b].m);
       } else {
         continue;
       }
@@ -126,6 +135,14 @@ void assign_lanes(Plan& p) {
       st[w.second].lane = l;
       load[l] += w.first;
     }
+    // the plan's own stream takes the heaviest lane: it then tends to finish
+    // last, and the join waits on helper lanes that are already done
+    const int heavy = static_cast<int>(std::max_element(load.begin(), load.end()) - load.begin());
+    if (heavy != 0)
+      for (const auto& w : work) {
+        int& l = st[w.second].lane;
+        l = l == heavy ? 0 : l == 0 ? heavy : l;
+      }
     p.lanes[seq] = nl;
   }
 }
@@ -136,6 +153,7 @@ void build_stages(Plan& p) {
   for (int seq = 0; seq < 2; ++seq) {
     std::vector<Stage>& st = p.stages[seq];
     st.clear();
+    st.push_back(Stage{3, 0, true});
     for (size_t b = 0; b < p.buckets.size(); ++b) {
       const Bucket& B = p.buckets[b];
       const bool f64 = seq == 0 || !B.fp32_ok || B.k == 1;
@@ -152,8 +170,17 @@ int stage_count(const Plan& p, int precision) {
   return static_cast<int>(p.stages[precision == STTSV_PREC_FP32 ? 1 : 0].size());
 }
 
+static hipError_t launch_permute(Plan& p, const double* x, const int32_t* done, hipStream_t s) {
+  if (p.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(permute_x, dim3(static_cast<unsigned>((p.n + 255) / 256)), dim3(256), 0, s, x,
+                     (const int32_t*)p.d_rid, (int64_t)p.n, p.d_xr, done);
+  return hipGetLastError();
+}
+
+// c.x: the caller's x for the permute stage, the rank-ordered copy for edge stages
 static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, double* y, hipStream_t s) {
   const EdgeTables& tab = edge_tables();
+  if (S.type == 3) return launch_permute(p, c.x, c.done, s);
   if (S.type == 0) {
     const Bucket& B = p.buckets[S.index];
     const BucketDesc& d = B.desc[S.f64 ? 0 : 1];
@@ -179,7 +206,7 @@ static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, 
 hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s) {
   const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
-  return launch_stage_call(p, S, EdgeCall{x, p.d_contrib, done, nullptr}, y, s);
+  return launch_stage_call(p, S, EdgeCall{S.type == 3 ? x : p.d_xr, p.d_contrib, done, nullptr}, y, s);
 }
 
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
@@ -199,10 +226,11 @@ int init_lanes(Plan& p) {
 
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
                         hipStream_t s) {
-  const EdgeCall c{x, p.d_contrib, done, gskip};
+  const EdgeCall c{p.d_xr, p.d_contrib, done, gskip};
   const int seq = precision == STTSV_PREC_FP32 ? 1 : 0;
   const int nl = (p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr ? 1 : p.lanes[seq];
-  hipError_t e = hipSuccess;
+  hipError_t e = launch_permute(p, x, done, s);
+  if (e != hipSuccess) return e;
   if (nl > 1) {
     // fork: every helper lane starts after the work already on s
     if ((e = hipEventRecord(p.ev_fork, s)) != hipSuccess) return e;
@@ -210,7 +238,7 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
       if ((e = hipStreamWaitEvent(p.aux[l], p.ev_fork, 0)) != hipSuccess) return e;
   }
   for (const Stage& S : p.stages[seq]) {
-    if (S.type == 2) continue;
+    if (S.type == 2 || S.type == 3) continue;
     const hipStream_t ls = nl > 1 && S.lane > 0 ? p.aux[S.lane - 1] : s;
     if ((e = launch_stage_call(p, S, c, nullptr, ls)) != hipSuccess) break;
   }
@@ -246,9 +274,12 @@ void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t*
     int64_t m = 0;
     for (int b : p.groups[S.index].buckets) m += p.buckets[b].m;
     *count = m;
-  } else {
+  } else if (S.type == 2) {
     *size = S.index;
     *count = p.levels[S.index].nchunks;
+  } else {
+    *size = 0;
+    *count = p.n;
   }
 }
 

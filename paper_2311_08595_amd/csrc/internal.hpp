@@ -145,7 +145,8 @@ struct GenGroup {
 
 // One launch of the STTSV sequence.
 struct Stage {
-  int type;      // 0 = per-bucket edge kernel, 1 = fused generic group, 2 = reduction level
+  int type;      // 0 = per-bucket edge kernel, 1 = fused generic group, 2 = reduction level,
+                 // 3 = x into degree-rank order
   int index;     // bucket, group or level
   bool f64;      // series type of an edge stage
   int lane = 0;  // stream lane of an edge stage (0 = the plan's stream)
@@ -186,7 +187,9 @@ struct Plan {
   std::vector<int32_t> tslot;
 
   // device buffers
-  int32_t* d_mem = nullptr;
+  int32_t* d_mem = nullptr;       // member slots as degree-rank positions (what the kernels gather by)
+  int32_t* d_rid = nullptr;       // vertex id at every degree-rank position
+  double* d_xr = nullptr;         // x in degree-rank order (written by the permute stage)
   std::vector<int32_t> vblock;    // vertex block of every vertex
   std::vector<int64_t> region;    // first contribution index of every block (+ nnz at the end)
   int32_t* d_loc = nullptr;       // contribution index of every member slot

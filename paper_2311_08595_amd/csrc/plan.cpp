@@ -13,6 +13,9 @@
 //     bucket k at slot_off(k) + j m_k + i, slot_off(k) = sum_{k'<k} k' m_k';
 //  7. node-major incidence lists: for each v the slots holding v, in
 //     canonical edge order;
+//  7a. the edge kernels gather x in degree-rank order (hubs first, so the hot
+//     part of x shares cache lines): on the device, member slots hold rank
+//     positions voff + rank, and every STTSV first copies x into that order;
 //  8. contribution storage: vertices (in index order) form blocks of about
 //     kRegionTarget incidences; each block owns a contiguous region, split
 //     into one part per die (workgroup w of a launch runs on die w mod 8),
@@ -191,6 +194,8 @@ void free_plan(Plan* p) {
   if (p == nullptr) return;
   free_solver(*p);
   (void)hipFree(p->d_mem);
+  (void)hipFree(p->d_rid);
+  (void)hipFree(p->d_xr);
   (void)hipFree(p->d_loc);
   (void)hipFree(p->d_glist);
   (void)hipFree(p->d_gid);
@@ -582,6 +587,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       P->tptr[u + 1] = P->tptr[u] + degs[g][v];
     }
   P->tslot.assign(nnz, 0);
+  std::vector<int32_t> memr(nnz, 0), rid(n, 0);
   std::vector<int32_t> gid;
   if (G > 1) gid.assign(m, 0);
   {
@@ -591,6 +597,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       const GraphInfo& I = P->graphs[g];
       Canon c;
       canonicalise(in, degs[g], c);
+      for (int32_t q = 0; q < in.n; ++q) rid[I.voff + q] = I.voff + c.inv_rank[q];
       for (int k = 1; k <= in.r; ++k) {
         const auto& ids = c.order[k];
         if (ids.empty()) continue;
@@ -606,6 +613,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
             const int32_t u = I.voff + c.inv_rank[a[j]];
             const int64_t s = B.slot_off + (int64_t)j * B.m + i;
             P->mem[s] = u;
+            memr[s] = I.voff + a[j];
             P->tslot[cur[u]++] = static_cast<int32_t>(s);
           }
         }
@@ -698,7 +706,11 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     free_plan(P);
     return code;
   };
-  if ((rc = upload(&P->d_mem, P->mem.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload(&P->d_mem, memr.data(), nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  memr.clear();
+  memr.shrink_to_fit();
+  if ((rc = upload(&P->d_rid, rid.data(), n, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload<double>(&P->d_xr, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_glist, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);

@@ -121,7 +121,9 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
   if (x == nullptr || reps < 1) return STTSV_EINVAL;
   load_cache(cache_path);
   const EdgeTables& tab = edge_tables();
-  const EdgeCall c{x, p.d_contrib, nullptr, nullptr};
+  // the edge kernels gather from the rank-ordered copy of x: the first stage makes it
+  if (launch_stage(p, 0, x, nullptr, STTSV_PREC_FP64, nullptr, p.stream) != hipSuccess) return STTSV_EHIP;
+  const EdgeCall c{p.d_xr, p.d_contrib, nullptr, nullptr};
   int count = 0;
   for (Bucket& B : p.buckets) {
     if (B.k < 4) continue;

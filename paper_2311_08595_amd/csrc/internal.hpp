@@ -103,9 +103,11 @@ const EdgeTables& edge_tables();
 // One level of the deterministic node reduction.
 struct ReduceLevel {
   int64_t nchunks = 0;
-  int32_t* d_start = nullptr;   // first input index of each chunk
-  int32_t* d_len = nullptr;     // chunk length (0 for an isolated vertex)
-  int32_t* d_dst = nullptr;     // >= 0: vertex id (final); < 0: -(partial index)-1
+  // one 16-byte descriptor per chunk (a single load for the 8 lanes of a
+  // chunk): x = first input index, y = length (0 for an isolated vertex),
+  // z = destination (>= 0: vertex id, final; < 0: -(partial index)-1;
+  // kNoDst: padding), w unused
+  int4* d_desc = nullptr;
   int64_t in_len = 0;           // length of this level's input array
   const int32_t* d_gather = nullptr;   // level 0: contribution index of each term
 };

@@ -205,9 +205,7 @@ void free_plan(Plan* p) {
     (void)hipFree(g.d_tasks);
   }
   for (auto& L : p->levels) {
-    (void)hipFree(L.d_start);
-    (void)hipFree(L.d_len);
-    (void)hipFree(L.d_dst);
+    (void)hipFree(L.d_desc);
   }
   for (double* d : p->d_partials) (void)hipFree(d);
   for (auto& b : p->buckets) {
@@ -722,9 +720,11 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     P->levels.push_back(L);
     ReduceLevel& D = P->levels.back();
     if (l == 0) D.d_gather = P->d_glist;
-    if ((rc = upload(&D.d_start, hl[l].start.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
-    if ((rc = upload(&D.d_len, hl[l].len.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
-    if ((rc = upload(&D.d_dst, hl[l].dst.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    {
+      std::vector<int4> desc(D.nchunks);
+      for (int64_t c = 0; c < D.nchunks; ++c) desc[c] = make_int4(hl[l].start[c], hl[l].len[c], hl[l].dst[c], 0);
+      if ((rc = upload(&D.d_desc, desc.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    }
     if (l + 1 < hl.size()) {
       double* part = nullptr;
       if ((rc = upload<double>(&part, nullptr, hl[l + 1].in_len, &P->device_bytes)) != STTSV_OK) return fail(rc);

@@ -23,9 +23,7 @@ constexpr int kPerLane = kChunk / kGroup;   // terms per lane
 static_assert(kChunk % kGroup == 0, "chunk must split evenly over the group");
 
 template <bool GATHER>
-__global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ start,
-                                                    const int32_t* __restrict__ len,
-                                                    const int32_t* __restrict__ dst, int64_t nchunks,
+__global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ desc, int64_t nchunks,
                                                     const int32_t* __restrict__ gather,
                                                     const double* __restrict__ in,
                                                     double* __restrict__ y, double* __restrict__ next,
@@ -34,11 +32,9 @@ __global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ 
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t c = gid / kGroup;
   const int j = static_cast<int>(gid % kGroup);
-  int32_t s = 0, l = 0;
-  if (c < nchunks) {
-    s = start[c];
-    l = len[c];
-  }
+  int4 dsc = make_int4(0, 0, kNoDst, 0);
+  if (c < nchunks) dsc = desc[c];
+  const int32_t s = dsc.x, l = dsc.y;
   int32_t idx[kPerLane];
 #pragma unroll
   for (int q = 0; q < kPerLane; ++q) {
@@ -53,7 +49,7 @@ __global__ void __launch_bounds__(256) reduce_level(const int32_t* __restrict__ 
   v += __shfl_down(v, 2, kGroup);
   v += __shfl_down(v, 1, kGroup);
   if (j == 0 && c < nchunks) {
-    const int32_t d = dst[c];
+    const int32_t d = dsc.z;
     if (d >= 0)
       y[d] = v;
     else if (d != kNoDst)
@@ -69,10 +65,10 @@ hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y
   const int64_t threads = L.nchunks * kGroup;
   const dim3 grid(static_cast<unsigned>((threads + 255) / 256));
   if (L.d_gather != nullptr)
-    hipLaunchKernelGGL(reduce_level<true>, grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst, L.nchunks,
+    hipLaunchKernelGGL(reduce_level<true>, grid, dim3(256), 0, s, (const int4*)L.d_desc, L.nchunks,
                        L.d_gather, in, y, next, done);
   else
-    hipLaunchKernelGGL(reduce_level<false>, grid, dim3(256), 0, s, L.d_start, L.d_len, L.d_dst, L.nchunks,
+    hipLaunchKernelGGL(reduce_level<false>, grid, dim3(256), 0, s, (const int4*)L.d_desc, L.nchunks,
                        nullptr, in, y, next, done);
   return hipGetLastError();
 }

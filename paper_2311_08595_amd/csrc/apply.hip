@@ -225,11 +225,11 @@ int init_lanes(Plan& p) {
 }
 
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s) {
-  const EdgeCall c{p.d_xr, p.d_contrib, done, gskip};
+                        hipStream_t s, XOrder order) {
+  const EdgeCall c{order == XOrder::kRank ? x : p.d_xr, p.d_contrib, done, gskip};
   const int seq = precision == STTSV_PREC_FP32 ? 1 : 0;
   const int nl = (p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr ? 1 : p.lanes[seq];
-  hipError_t e = launch_permute(p, x, done, s);
+  hipError_t e = order == XOrder::kVertex ? launch_permute(p, x, done, s) : hipSuccess;
   if (e != hipSuccess) return e;
   if (nl > 1) {
     // fork: every helper lane starts after the work already on s
@@ -253,11 +253,11 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
   return e;
 }
 
-hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s) {
-  const EdgeCall c{nullptr, p.d_contrib, done, nullptr};
-  for (const Stage& S : p.stages[0]) {
-    if (S.type != 2) continue;
-    const hipError_t e = launch_stage_call(p, S, c, y, s);
+hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out) {
+  for (size_t l = 0; l < p.levels.size(); ++l) {
+    const double* in = l == 0 ? p.d_contrib : p.d_partials[l - 1];
+    double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
+    const hipError_t e = launch_reduce_level(p.levels[l], in, y, next, done, s, rank_out);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

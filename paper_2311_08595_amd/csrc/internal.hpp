@@ -106,7 +106,8 @@ struct ReduceLevel {
   // one 16-byte descriptor per chunk (a single load for the 8 lanes of a
   // chunk): x = first input index, y = length (0 for an isolated vertex),
   // z = destination (>= 0: vertex id, final; < 0: -(partial index)-1;
-  // kNoDst: padding), w unused
+  // kNoDst: padding), w = the same with the vertex's degree-rank position
+  // in place of its id (the solver keeps its vectors in that order)
   int4* d_desc = nullptr;
   int64_t in_len = 0;           // length of this level's input array
   const int32_t* d_gather = nullptr;   // level 0: contribution index of each term
@@ -236,14 +237,19 @@ int assign_places(Plan& p);   // contribution places for the current kernel choi
 int set_reuse(Plan& p, Bucket& b, bool by_flag);   // prefix-reuse runs of a bucket (plan.cpp)
 // The edge launches of one precision (per-graph skip flags, nullable), and
 // the reduction alone: the solver runs both precisions' edge launches then
-// one reduction per iteration.
+// one reduction per iteration.  launch_edges first copies x into degree-rank
+// order unless permute is false (the copy of an earlier call is still valid).
+// x order of an edge launch: the caller's vertex order (copied into rank
+// order first), already in rank order, or copied by an earlier launch.
+enum class XOrder { kVertex, kRank, kCopied };
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s);
-hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s);
+                        hipStream_t s, XOrder order = XOrder::kVertex);
+// rank_out: write y in degree-rank order instead of vertex order.
+hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false);
 
 // reduction kernels (reduce.hip)
 hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
-                               const int32_t* done, hipStream_t s);
+                               const int32_t* done, hipStream_t s, bool rank_out = false);
 
 // autotuner (tune.cpp)
 int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t* tuned);

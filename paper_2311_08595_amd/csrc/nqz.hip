@@ -158,6 +158,25 @@ __global__ void __launch_bounds__(kRedBlock) scale_into(Solver S, const double* 
   for (int v = vb.v0; v < vb.vend; v += vb.stride) dst[v] = src[v] * f;
 }
 
+// The solver keeps x, z, w in degree-rank order (position q holds vertex
+// rid[q]; each graph's positions are its own vertex range), so its STTSV
+// needs no reordering: these two kernels convert at entry and exit.
+__global__ void __launch_bounds__(kRedBlock) scale_from_vertex_order(Solver S, const double* src,
+                                                                     const int32_t* __restrict__ rid, double* dst) {
+  const VBlock vb = vblock(S);
+  const GCtrl& c = S.ctrl[vb.g];
+  if (c.done) return;
+  const double f = c.inv_wmax;
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) dst[v] = src[rid[v]] * f;
+}
+
+__global__ void __launch_bounds__(kRedBlock) divide_to_vertex_order(Solver S, const double* x,
+                                                                    const int32_t* __restrict__ rid, double* out) {
+  const VBlock vb = vblock(S);
+  const double s = S.sums[vb.g];
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) out[rid[v]] = x[v] / s;
+}
+
 __global__ void __launch_bounds__(kRedBlock) fill_ones(double* dst, int n) {
   const int v = blockIdx.x * kRedBlock + threadIdx.x;
   if (v < n) dst[v] = 1.0;
@@ -206,7 +225,10 @@ __global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
   __shared__ double sh[kRedBlock];
   const int g = blockIdx.x;
   GCtrl& c = S.ctrl[g];
-  if (c.done) return;
+  if (c.done) {
+    if (threadIdx.x == 0 && S.G == 1) S.sctrl->all_done = 1;
+    return;
+  }
   const int b0 = S.gblk0[g], nb = S.gnblk[g];
   double lo = INFINITY, hi = -INFINITY, wm = 0.0, bad = 0.0;
   for (int b = threadIdx.x; b < nb; b += kRedBlock) {
@@ -224,6 +246,7 @@ __global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
     c.done = 1;
     c.status = STTSV_ENUMERIC;
     S.skip64[g] = S.skip32[g] = 1;
+    if (S.G == 1) S.sctrl->all_done = 1;   // one graph: no separate all-done pass
     return;
   }
   c.inv_wmax = 1.0 / wm;
@@ -253,6 +276,7 @@ __global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
     c.status = STTSV_ENOTCONV;
   }
   if (c.done) S.skip64[g] = S.skip32[g] = 1;
+  if (S.G == 1) S.sctrl->all_done = c.done;
 }
 
 // all_done = every graph done (single block)
@@ -283,23 +307,17 @@ __global__ void __launch_bounds__(kRedBlock) sum_final(Solver S) {
   if (threadIdx.x == 0) S.sums[g] = acc;
 }
 
-__global__ void __launch_bounds__(kRedBlock) divide_by(Solver S, const double* x, double* out) {
-  const VBlock vb = vblock(S);
-  const double s = S.sums[vb.g];
-  for (int v = vb.v0; v < vb.vend; v += vb.stride) out[v] = x[v] / s;
-}
-
 // One NQZ iteration (all launches on S.s).
 hipError_t enqueue_iteration(Plan& p, Solver& S, int schedule) {
   hipError_t e;
   const int32_t* all_done = &S.sctrl->all_done;
   if (schedule == STTSV_SOLVE_FP32_FP64)
-    if ((e = launch_edges(p, S.x, STTSV_PREC_FP32, all_done, S.skip32, S.s)) != hipSuccess) return e;
-  if ((e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s)) != hipSuccess) return e;
-  if ((e = launch_reduction(p, S.z, all_done, S.s)) != hipSuccess) return e;
+    if ((e = launch_edges(p, S.x, STTSV_PREC_FP32, all_done, S.skip32, S.s, XOrder::kRank)) != hipSuccess) return e;
+  if ((e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s, XOrder::kRank)) != hipSuccess) return e;
+  if ((e = launch_reduction(p, S.z, all_done, S.s, true)) != hipSuccess) return e;
   hipLaunchKernelGGL((nqz_stats<true>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<true>), dim3(S.G), dim3(kRedBlock), 0, S.s, S);
-  hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
+  if (S.G > 1) hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
   return hipGetLastError();
 }
@@ -407,15 +425,16 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
   } else {
     hipLaunchKernelGGL(init_stats, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, x0);
     hipLaunchKernelGGL(init_final, dim3(G), dim3(kRedBlock), 0, S.s, S);
-    hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, x0, S.x);
+    hipLaunchKernelGGL(scale_from_vertex_order, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, x0,
+                       (const int32_t*)p.d_rid, S.x);
   }
   const int first_prec = o.schedule == STTSV_SOLVE_FP32_FP64 ? STTSV_PREC_FP32 : STTSV_PREC_FP64;
   const int32_t* first_skip = first_prec == STTSV_PREC_FP32 ? S.skip32 : S.skip64;
-  if ((rc = hip_rc(launch_edges(p, S.x, first_prec, nullptr, first_skip, S.s))) != STTSV_OK) return rc;
-  if ((rc = hip_rc(launch_reduction(p, S.z, nullptr, S.s))) != STTSV_OK) return rc;
+  if ((rc = hip_rc(launch_edges(p, S.x, first_prec, nullptr, first_skip, S.s, XOrder::kRank))) != STTSV_OK) return rc;
+  if ((rc = hip_rc(launch_reduction(p, S.z, nullptr, S.s, true))) != STTSV_OK) return rc;
   hipLaunchKernelGGL((nqz_stats<false>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<false>), dim3(G), dim3(kRedBlock), 0, S.s, S);
-  hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
+  if (G > 1) hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
   if (hipGetLastError() != hipSuccess) return STTSV_EHIP;
 
@@ -461,7 +480,8 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
   // x_out = x~ / ||x~||_1 per graph
   hipLaunchKernelGGL(sum_stage, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.x);
   hipLaunchKernelGGL(sum_final, dim3(G), dim3(kRedBlock), 0, S.s, S);
-  hipLaunchKernelGGL(divide_by, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.x, x_out);
+  hipLaunchKernelGGL(divide_to_vertex_order, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.x,
+                     (const int32_t*)p.d_rid, x_out);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
 
   // overall status: the worst of the graphs' (EINVAL > ENUMERIC > ENOTCONV > OK)

@@ -708,6 +708,8 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   memr.clear();
   memr.shrink_to_fit();
   if ((rc = upload(&P->d_rid, rid.data(), n, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  std::vector<int32_t> rpos(n);   // degree-rank position of every vertex
+  for (int32_t q = 0; q < n; ++q) rpos[rid[q]] = q;
   if ((rc = upload<double>(&P->d_xr, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_glist, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
@@ -722,7 +724,10 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     if (l == 0) D.d_gather = P->d_glist;
     {
       std::vector<int4> desc(D.nchunks);
-      for (int64_t c = 0; c < D.nchunks; ++c) desc[c] = make_int4(hl[l].start[c], hl[l].len[c], hl[l].dst[c], 0);
+      for (int64_t c = 0; c < D.nchunks; ++c) {
+        const int32_t d = hl[l].dst[c];
+        desc[c] = make_int4(hl[l].start[c], hl[l].len[c], d, d >= 0 ? rpos[d] : d);
+      }
       if ((rc = upload(&D.d_desc, desc.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
     }
     if (l + 1 < hl.size()) {

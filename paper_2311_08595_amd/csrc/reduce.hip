@@ -22,7 +22,7 @@ constexpr int kGroup = 8;                   // lanes per chunk
 constexpr int kPerLane = kChunk / kGroup;   // terms per lane
 static_assert(kChunk % kGroup == 0, "chunk must split evenly over the group");
 
-template <bool GATHER>
+template <bool GATHER, bool RANK>
 __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ desc, int64_t nchunks,
                                                     const int32_t* __restrict__ gather,
                                                     const double* __restrict__ in,
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
   v += __shfl_down(v, 2, kGroup);
   v += __shfl_down(v, 1, kGroup);
   if (j == 0 && c < nchunks) {
-    const int32_t d = dsc.z;
+    const int32_t d = RANK ? dsc.w : dsc.z;
     if (d >= 0)
       y[d] = v;
     else if (d != kNoDst)
@@ -60,16 +60,24 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
 }  // namespace
 
 hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
-                               const int32_t* done, hipStream_t s) {
+                               const int32_t* done, hipStream_t s, bool rank_out) {
   if (L.nchunks == 0) return hipSuccess;
   const int64_t threads = L.nchunks * kGroup;
   const dim3 grid(static_cast<unsigned>((threads + 255) / 256));
-  if (L.d_gather != nullptr)
-    hipLaunchKernelGGL(reduce_level<true>, grid, dim3(256), 0, s, (const int4*)L.d_desc, L.nchunks,
-                       L.d_gather, in, y, next, done);
-  else
-    hipLaunchKernelGGL(reduce_level<false>, grid, dim3(256), 0, s, (const int4*)L.d_desc, L.nchunks,
-                       nullptr, in, y, next, done);
+  const int4* d = L.d_desc;
+  if (L.d_gather != nullptr) {
+    if (rank_out)
+      hipLaunchKernelGGL((reduce_level<true, true>), grid, dim3(256), 0, s, d, L.nchunks, L.d_gather, in, y, next, done);
+    else
+      hipLaunchKernelGGL((reduce_level<true, false>), grid, dim3(256), 0, s, d, L.nchunks, L.d_gather, in, y, next,
+                         done);
+  } else {
+    if (rank_out)
+      hipLaunchKernelGGL((reduce_level<false, true>), grid, dim3(256), 0, s, d, L.nchunks, nullptr, in, y, next, done);
+    else
+      hipLaunchKernelGGL((reduce_level<false, false>), grid, dim3(256), 0, s, d, L.nchunks, nullptr, in, y, next,
+                         done);
+  }
   return hipGetLastError();
 }
 

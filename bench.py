@@ -161,7 +161,9 @@ def stage_kernel(s, prec, r):
     if s["kind"] == 1:
         return "edge_generic<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
     if s["kind"] == 2:
-        return ("reduce_level<true>" if s["size"] == 0 else "reduce_level<false>"), s["count"] * 8
+        if s["size"] == 0:
+            return "reduce_level0<true, false>", None
+        return "reduce_level<false, false>", s["count"] * 8
     if s["kind"] == 3:
         return "permute_x", (s["count"] + 255) // 256 * 256
     return None, None

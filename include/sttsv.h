@@ -326,6 +326,9 @@ int sttsv_mpnn_warm_start(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, double* x0);
                                /*             (INT32_MIN: size runs in FP64), for */
                                /*             the first graph's order r           */
 #define STTSV_Q_BUCKET_R    8  /* int64[nb]  tensor order of each bucket          */
+#define STTSV_Q_CONTRIB    10  /* double[nnz] the per-incidence contributions of  */
+                               /*            the last apply, in node-major order  */
+                               /*            (synchronises the plan's stream)      */
 #define STTSV_Q_BUCKET_RUNS 9  /* int64[nb]  FP64 prefix-reuse runs of each bucket */
                                /*            (0: the bucket does not reuse; else */
                                /*            m - runs edges take a shared prefix) */

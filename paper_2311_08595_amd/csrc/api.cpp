@@ -204,6 +204,15 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
       }
       case STTSV_Q_WEIGHTS:
         return copy_out<double, double>(p.weights, out, count);
+      case STTSV_Q_CONTRIB: {
+        if (count != p.nnz) return STTSV_EINVAL;
+        std::vector<double> c(p.nnz), v(p.nnz);
+        if (hipStreamSynchronize(p.stream) != hipSuccess ||
+            (p.nnz > 0 && hipMemcpy(c.data(), p.d_contrib, sizeof(double) * p.nnz, hipMemcpyDeviceToHost) != hipSuccess))
+          return STTSV_EHIP;
+        for (int64_t q = 0; q < p.nnz; ++q) v[q] = c[p.glist[q]];
+        return copy_out<double, double>(v, out, count);
+      }
       case STTSV_Q_SCALE_EXP: {
         const int r0 = p.graphs[0].r;
         std::vector<int64_t> v(r0 + 1, INT32_MIN);

@@ -25,7 +25,6 @@ constexpr int kSmallBlock = 256;         // threads per block of the other edge 
 constexpr int kChunk = 32;               // reduction chunk length (fixed: part of the format)
 constexpr int kXcd = 8;                  // accelerator dies (XCDs); workgroups go round-robin over them
 constexpr int kRegionTarget = 1 << 17;   // contributions per vertex block (1 MiB of FP64)
-constexpr int kReduceChunksPerBlock = 32;   // level-0 chunks per 256-thread reduction workgroup
 constexpr int32_t kNoDst = INT32_MIN;    // padding chunk of the reduction schedule: no output
 constexpr int kRunMax = 4;               // prefix reuse: edges per run (per thread)
 constexpr int kGenRanges = 8;            // window ranges of the fused generic kernels
@@ -109,6 +108,10 @@ struct ReduceLevel {
   // kNoDst: padding), w = the same with the vertex's degree-rank position
   // in place of its id (the solver keeps its vectors in that order)
   int4* d_desc = nullptr;
+  // level 0: workgroup table {first chunk, lanes per chunk (8, 4, 2, 1),
+  // chunks, unused}; null for the other levels (8 lanes per chunk)
+  int4* d_wg = nullptr;
+  int64_t nwg = 0;
   int64_t in_len = 0;           // length of this level's input array
   const int32_t* d_gather = nullptr;   // level 0: contribution index of each term
 };
@@ -197,6 +200,7 @@ struct Plan {
   std::vector<int64_t> region;    // first contribution index of every block (+ nnz at the end)
   int32_t* d_loc = nullptr;       // contribution index of every member slot
   int32_t* d_glist = nullptr;     // contribution index of every node-major incidence
+  std::vector<int32_t> glist;     // host copy
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
   double* d_contrib = nullptr;    // contributions, one region per vertex block
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)

@@ -38,38 +38,60 @@
 namespace sttsv {
 namespace {
 
-// One level of the reduction schedule (host side).
+// One level of the reduction schedule (host side); wg: level-0 workgroup
+// table {first chunk, lanes per chunk, chunks} (empty for other levels).
 struct HostLevel {
   std::vector<int32_t> start, len, dst;
+  std::vector<int4> wg;
   int64_t in_len = 0;
 };
 
-// Launch order of reduction level 0.  Workgroup w takes chunks
-// [kReduceChunksPerBlock w, +kReduceChunksPerBlock) and is dispatched to die
-// w mod kXcd.  Each die receives whole vertex blocks (largest first, to the
-// least-loaded die) and works through them in turn, so the region it gathers
-// from stays in its own L2; a block heavier than half a die's share (a hub,
-// whose terms are contiguous anyway) is dealt over all dies.  Inside a block
-// the chunks go longest first, so the lanes of a wave do similar work.
-// Dies with fewer workgroups are padded with empty chunks (dst = kNoDst).
+// Lanes that sum one level-0 chunk of length l: 8 for long chunks, fewer for
+// chunks that fit (the kernel then adds the missing partial sums as the
+// zeros they are, so the tree and its bits do not change).
+int group_lanes(int32_t l) { return l <= 1 ? 1 : l == 2 ? 2 : l <= 4 ? 4 : 8; }
+
+// Launch order of reduction level 0.  Workgroup w (256 threads) takes
+// 256 / lanes consecutive chunks of one vertex block that all use the same
+// lane count, and is dispatched to die w mod kXcd.  Each die receives whole
+// vertex blocks (largest first, to the least-loaded die) and works through
+// them in turn, so the region it gathers from stays in its own L2; a block
+// heavier than half a die's share (a hub, whose terms are contiguous anyway)
+// is dealt over all dies.  Inside a block the chunks go longest first, so
+// the lanes of a wave do similar work.  Dies with fewer workgroups get empty
+// ones.
 HostLevel xcd_schedule(const HostLevel& L, const std::vector<int32_t>& cblock) {
-  constexpr int G = kReduceChunksPerBlock;
+  constexpr int T = 256;
   const int64_t nc = static_cast<int64_t>(L.len.size());
   int32_t nb = 0;
   for (int64_t c = 0; c < nc; ++c) nb = std::max(nb, cblock[c] + 1);
   std::vector<std::vector<int64_t>> bc(nb);
   for (int64_t c = 0; c < nc; ++c) bc[cblock[c]].push_back(c);
+  struct Wg {
+    int32_t block;
+    int64_t first;   // first chunk within the block's sorted list
+    int32_t count, lanes;
+  };
+  std::vector<std::vector<Wg>> bw(nb);
   int64_t total = 0;
-  for (auto& v : bc) {
-    std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t b) { return L.len[a] > L.len[b]; });
-    total += (static_cast<int64_t>(v.size()) + G - 1) / G;
+  for (int32_t b = 0; b < nb; ++b) {
+    auto& v = bc[b];
+    std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t q) { return L.len[a] > L.len[q]; });
+    for (size_t i = 0; i < v.size();) {
+      const int g = group_lanes(L.len[v[i]]);
+      size_t j = i;
+      while (j < v.size() && group_lanes(L.len[v[j]]) == g && j - i < static_cast<size_t>(T / g)) ++j;
+      bw[b].push_back(Wg{b, static_cast<int64_t>(i), static_cast<int32_t>(j - i), g});
+      i = j;
+    }
+    total += static_cast<int64_t>(bw[b].size());
   }
   std::vector<int32_t> order(nb);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return bc[a].size() > bc[b].size(); });
+                   [&](int32_t a, int32_t q) { return bw[a].size() > bw[q].size(); });
   const int64_t big = std::max<int64_t>(1, total / (2 * kXcd));
-  std::vector<std::vector<std::pair<int32_t, int64_t>>> queue(kXcd);   // (block, first chunk in block)
+  std::vector<std::vector<Wg>> queue(kXcd);
   auto least = [&]() {
     int x = 0;
     for (int y = 1; y < kXcd; ++y)
@@ -77,12 +99,11 @@ HostLevel xcd_schedule(const HostLevel& L, const std::vector<int32_t>& cblock) {
     return x;
   };
   for (int32_t b : order) {
-    const int64_t ng = (static_cast<int64_t>(bc[b].size()) + G - 1) / G;
-    if (ng > big) {
-      for (int64_t g = 0; g < ng; ++g) queue[least()].emplace_back(b, g * G);
+    if (static_cast<int64_t>(bw[b].size()) > big) {
+      for (const Wg& w : bw[b]) queue[least()].push_back(w);
     } else {
       const int x = least();
-      for (int64_t g = 0; g < ng; ++g) queue[x].emplace_back(b, g * G);
+      for (const Wg& w : bw[b]) queue[x].push_back(w);
     }
   }
   size_t rounds = 0;
@@ -91,20 +112,18 @@ HostLevel xcd_schedule(const HostLevel& L, const std::vector<int32_t>& cblock) {
   R.in_len = L.in_len;
   for (size_t t = 0; t < rounds; ++t)
     for (int x = 0; x < kXcd; ++x) {
-      int64_t filled = 0;
+      const int32_t c0 = static_cast<int32_t>(R.len.size());
       if (t < queue[x].size()) {
-        const auto& v = bc[queue[x][t].first];
-        for (int64_t i = queue[x][t].second; i < std::min<int64_t>(queue[x][t].second + G, v.size()); ++i) {
+        const Wg& w = queue[x][t];
+        const auto& v = bc[w.block];
+        for (int64_t i = w.first; i < w.first + w.count; ++i) {
           R.start.push_back(L.start[v[i]]);
           R.len.push_back(L.len[v[i]]);
           R.dst.push_back(L.dst[v[i]]);
-          ++filled;
         }
-      }
-      for (; filled < G; ++filled) {
-        R.start.push_back(0);
-        R.len.push_back(0);
-        R.dst.push_back(kNoDst);
+        R.wg.push_back(make_int4(c0, w.lanes, w.count, 0));
+      } else {
+        R.wg.push_back(make_int4(c0, 8, 0, 0));
       }
     }
   return R;
@@ -206,6 +225,7 @@ void free_plan(Plan* p) {
   }
   for (auto& L : p->levels) {
     (void)hipFree(L.d_desc);
+    (void)hipFree(L.d_wg);
   }
   for (double* d : p->d_partials) (void)hipFree(d);
   for (auto& b : p->buckets) {
@@ -495,6 +515,7 @@ int assign_places(Plan& P) {
   if (nnz > 0 && (hipMemcpy(P.d_loc, loc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess ||
                   hipMemcpy(P.d_glist, glist.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess))
     return STTSV_EHIP;
+  P.glist = std::move(glist);
   return STTSV_OK;
 }
 
@@ -729,6 +750,10 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
         desc[c] = make_int4(hl[l].start[c], hl[l].len[c], d, d >= 0 ? rpos[d] : d);
       }
       if ((rc = upload(&D.d_desc, desc.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    }
+    if (!hl[l].wg.empty()) {
+      D.nwg = static_cast<int64_t>(hl[l].wg.size());
+      if ((rc = upload(&D.d_wg, hl[l].wg.data(), hl[l].wg.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
     }
     if (l + 1 < hl.size()) {
       double* part = nullptr;

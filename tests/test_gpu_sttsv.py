@@ -297,6 +297,54 @@ def test_prefix_reuse_bitwise_equal(torch_cuda):
         assert _relerr(y, ref_y) <= TOL["fp64"]
 
 
+def _tree_sum(terms):
+    # the reduction tree of one vertex: chunks of 32 consecutive terms; in a
+    # chunk, s_l = terms l, l+8, l+16, l+24 added left to right from +0.0,
+    # chunk sum ((s0+s4)+(s2+s6))+((s1+s5)+(s3+s7)); chunk sums feed the next
+    # level the same way
+    def chunk(ts):
+        s = []
+        for lane in range(8):
+            v = 0.0
+            for u in range(4):
+                if lane + 8 * u < len(ts):
+                    v += ts[lane + 8 * u]
+            s.append(v)
+        return ((s[0] + s[4]) + (s[2] + s[6])) + ((s[1] + s[5]) + (s[3] + s[7]))
+    vals = [float(t) for t in terms]
+    while len(vals) > 32:
+        vals = [chunk(vals[i:i + 32]) for i in range(0, len(vals), 32)]
+    return chunk(vals)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_reduction_tree_is_the_documented_one(torch_cuda, prec):
+    # y_v equals, bit for bit, the fixed tree over v's contributions in
+    # canonical order -- whatever lanes and launch order the kernels use;
+    # a hub of degree 2100 exercises three levels, isolated vertices give +0.0
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    rng = np.random.default_rng(17)
+    n, r = 3000, 6
+    edges = []
+    for _ in range(2100):                      # hub 0 in 2100 edges
+        k = int(rng.integers(2, 5))
+        edges.append([0] + list(rng.choice(np.arange(1, 2500), size=k - 1, replace=False)))
+    for _ in range(6000):
+        k = int(rng.integers(1, 7))
+        edges.append(list(rng.choice(np.arange(1, 2500), size=k, replace=False)))
+    eptr, eidx = _csr(edges)
+    x = 1.0 - rng.random(n)
+    with st.Plan(eptr, eidx, n, r) as plan:
+        y = plan.apply(torch.tensor(x, dtype=torch.float64, device="cuda"), precision=prec).cpu().numpy()
+        contrib = plan.query(_lib.Q_CONTRIB)
+        tptr = plan.query(_lib.Q_TPTR)
+    got = np.array([_tree_sum(contrib[tptr[v]:tptr[v + 1]]) for v in range(n)])
+    assert got.tobytes() == y.tobytes()
+    assert np.all(y[2500:] == 0.0) and not np.signbit(y[2500:]).any()
+
+
 def test_autotune_keeps_bits(tmp_path):
     # the tuner only chooses among bitwise-identical variants
     import paper_2311_08595_amd as st

@@ -96,8 +96,10 @@ typedef struct {
  * The arrays are copied; the caller may free them on return.  The plan
  * holds all device buffers (member layout, per-incidence contributions,
  * node-major incidence lists, reduction schedule, weight table
- * w(e)/|beta(e)| (r-1)! per edge size).  Blocking (uploads are synchronous).
- * Errors: EINVAL (malformed input), ENOTSUP (r out of range), ENOMEM, EHIP.
+ * w(e)/|beta(e)| (r-1)! per edge size, the degree-rank copy of x) and is
+ * used by one host thread at a time.  Blocking (uploads are synchronous).
+ * Errors: EINVAL (malformed input), ENOTSUP (r out of range, or m, n or nnz
+ * at or above 2^31), ENOMEM, EHIP.
  */
 int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n,
                int32_t r, const sttsv_opts* opts, sttsv_plan_t* out);

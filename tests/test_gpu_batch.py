@@ -50,6 +50,29 @@ def test_batch_apply_bitwise_equals_single(prec):
         assert np.max(np.abs(y1 - ref) / np.where(ref != 0, np.abs(ref), 1)) <= tol
 
 
+def test_batch_flags_keep_bits():
+    # prefix reuse (runs never cross graphs: they share their first two
+    # vertices) and the one-stream launch order leave every bit of y alone
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    gs = []
+    for g in range(5):
+        w = wl.zipf_powerlaw(seed=70 + g, n=40000, m=200000)
+        gs.append((w["eptr"], w["eidx"], w["n"], w["r"]))
+    rng = np.random.default_rng(9)
+    x = torch.tensor(1.0 - rng.random(sum(g[2] for g in gs)), dtype=torch.float64, device="cuda")
+    out = {}
+    for flags in (0, _lib.FLAG_PREFIX_REUSE, _lib.FLAG_ONE_STREAM):
+        with st.Plan.batch(gs, flags=flags) as pb:
+            if flags == _lib.FLAG_PREFIX_REUSE:
+                assert np.any(pb.query(_lib.Q_BUCKET_RUNS) > 0)
+            if flags == 0:
+                assert pb.info()["lanes"] > 1
+            out[flags] = pb.apply(x).cpu().numpy().tobytes()
+    assert out[0] == out[_lib.FLAG_PREFIX_REUSE] == out[_lib.FLAG_ONE_STREAM]
+
+
 @pytest.mark.parametrize("schedule", ["fp64", "fp32_fp64"])
 def test_batch_solve_matches_single_and_oracle(schedule):
     import torch

@@ -478,6 +478,23 @@ def main():
         out["solve"] = solve
     if not a.no_batch:
         out["batched"] = bench_batch(a)
+        # the warm-start target: warm-started batched FP32->FP64 solve (inference
+        # included) against the plain FP64 solves of the same graphs one by one,
+        # and, for the n=1e6 graph, the warm-started FP32->FP64 single solve
+        # against its plain FP64 solve
+        b = out["batched"]
+        tgt = {}
+        if "solve_batch_net_start_fp32_fp64" in b:
+            w_s = b["solve_batch_net_start_fp32_fp64"]["seconds"]
+            tgt["batched_warm_fp32_fp64_s"] = w_s
+            tgt["single_plain_fp64_sum_s"] = b["solve_single_sum_fp64_s"]
+            tgt["batched_met"] = w_s < b["solve_single_sum_fp64_s"]
+        sv = out.get("solve", {})
+        if "net_start_fp32_fp64" in sv:
+            tgt["n1e6_warm_fp32_fp64_s"] = sv["net_start_fp32_fp64"]["seconds"]
+            tgt["n1e6_plain_fp64_s"] = sv["fp64"]["seconds"]
+            tgt["n1e6_met"] = sv["net_start_fp32_fp64"]["seconds"] < sv["fp64"]["seconds"]
+        out["warm_start_target"] = tgt
     if not a.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_edges)

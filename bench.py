@@ -366,8 +366,13 @@ def main():
             if st_["kind"] == 2:
                 st_["in_len"] = prev
                 prev = st_["count"]
-        res[prec] = dict(ms=dt * 1e3, stages=stages)
+        res[prec] = dict(ms=dt * 1e3, stages=stages, y=yd.clone())
         log("[bench]   %s: %.3f ms/STTSV, %.3e hyperedges/s" % (prec, dt * 1e3, m / dt))
+    # error of the FP32-series result against the FP64 path (which the tests
+    # hold to 1e-12 of the oracle), over vertices with y != 0
+    y64, y32 = res["fp64"].pop("y"), res["fp32"].pop("y")
+    nz = y64 != 0
+    fp32_err = float(((y32[nz] - y64[nz]).abs() / y64[nz].abs()).max())
 
     out = {
         "metric": "STTSV hyperedges/s",
@@ -396,7 +401,7 @@ def main():
     best32, roof32 = roofline_of(res["fp32"]["stages"], res["fp32"]["work"], "fp32", r)
     roof32["avg_kernel_ms"] = best32["ms"]
     out["fp32_series"] = {"value": m / (res["fp32"]["ms"] * 1e-3), "ms_per_step": res["fp32"]["ms"],
-                          "roofline": roof32}
+                          "max_rel_err_vs_fp64": fp32_err, "roofline": roof32}
     out["stages_fp64_ms"] = [(s["kind"], s["size"], s["count"], round(s["ms"], 5)) for s in res["fp64"]["stages"]]
     out["stages_fp32_ms"] = [(s["kind"], s["size"], s["count"], round(s["ms"], 5)) for s in res["fp32"]["stages"]]
     out["plan_s"] = plan_s
@@ -440,15 +445,20 @@ def main():
                 p2.solve(tol=1e-8, schedule=sched, x0=x0)   # warm-up (graph capture)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                _, info = p2.solve(tol=1e-8, schedule=sched, x0=x0)
+                xs, info = p2.solve(tol=1e-8, schedule=sched, x0=x0)
                 dt = time.perf_counter() - t0
+                out_x[(sched, x0 is None)] = xs
                 return dict(seconds=dt + pre, solve_seconds=dt, iterations=info["iterations"],
                             iters_fp32=info["iters_fp32"], iters_fp64=info["iters_fp64"],
                             lambda_max=info["lambda_max"], criterion=info["criterion"])
+            out_x = {}
             for sched in ("fp64", "fp32_fp64"):
                 solve[sched] = timed(sched)
                 log("[bench]   solve %s (uniform start): %.4f s, %d iterations"
                     % (sched, solve[sched]["seconds"], solve[sched]["iterations"]))
+            # the FP32->FP64 result against the FP64 one (same tolerance, same start)
+            xa, xb = out_x[("fp64", True)], out_x[("fp32_fp64", True)]
+            solve["fp32_fp64"]["max_rel_diff_vs_fp64"] = float(((xb - xa).abs() / xa).max())
             # control: degree start d^(1/(r-1)) (the first NQZ iterate from the uniform start)
             d = np.bincount(i2, minlength=n2).astype(np.float64)
             xdeg = torch.tensor(d ** (1.0 / (r - 1)), dtype=torch.float64, device="cuda")

@@ -59,7 +59,7 @@ typedef struct sttsv_plan_s* sttsv_plan_t;
                                    /* resident ones; results are bitwise identical    */
 #define STTSV_FLAG_ONE_STREAM   2  /* launch every edge kernel on the plan's stream.  */
                                    /* By default the edge launches are spread over   */
-                                   /* the plan's stream and three helper streams of  */
+                                   /* the plan's stream and two helper streams of    */
                                    /* default priority (event fork / join, so work   */
                                    /* stays ordered on the plan's stream); results   */
                                    /* are bitwise identical either way               */

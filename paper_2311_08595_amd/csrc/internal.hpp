@@ -161,7 +161,7 @@ struct Stage {
 // Edge launches run on up to kLanes streams: the plan's own and kLanes - 1
 // helpers of default priority, forked from and joined back to the plan's
 // stream with events.
-constexpr int kLanes = 4;
+constexpr int kLanes = 3;
 
 // One hypergraph of a (possibly batched) plan.
 struct GraphInfo {

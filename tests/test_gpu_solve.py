@@ -66,7 +66,8 @@ def test_stream_lanes_solve_bitwise(big_graph, schedule):
     out = []
     for flags in (0, _lib.FLAG_ONE_STREAM, _lib.FLAG_PREFIX_REUSE):
         with st.Plan(eptr, eidx, n, r, flags=flags) as plan:
-            assert plan.info()["lanes"] == (1 if flags == _lib.FLAG_ONE_STREAM else 4)
+            lanes = plan.info()["lanes"]
+            assert lanes == 1 if flags == _lib.FLAG_ONE_STREAM else lanes > 1
             x, info = plan.solve(tol=1e-10, schedule=schedule)
             out.append((x.cpu().numpy().tobytes(), info["iterations"], info["iters_fp32"]))
     assert out[0] == out[1] == out[2]

@@ -106,14 +106,17 @@ def stage_work(stages, bucket_k, bucket_m, r):
     return out
 
 
+STTSV_SOURCES = ("edge_", "apply.hip", "reduce.hip", "internal.hpp", "plan.cpp")
+
+
 def source_fingerprint():
-    """sha256 over the kernel and planner sources: traffic figures taken from
-    counters apply only while it is unchanged."""
+    """sha256 over the sources of the STTSV kernels and the layout they run
+    on: traffic figures taken from counters apply only while it is unchanged."""
     import hashlib
     d = os.path.join(ROOT, "paper_2311_08595_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".inc", ".hpp", ".cpp")):
+        if f.startswith(STTSV_SOURCES) and f.endswith((".hip", ".inc", ".hpp", ".cpp")):
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())

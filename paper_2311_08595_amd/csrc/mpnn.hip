@@ -97,18 +97,26 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __shfl(v, 0, 64);
 }
 
-// features (one thread per vertex)
-__global__ void feat_kernel(Graph g) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= g.n) return;
+// features (one wave per vertex: lane l sums the vertex's edges l, l + 64,
+// ..., then a fixed halving reduction across the wave)
+__global__ void __launch_bounds__(256) feat_kernel(Graph g) {
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= g.n) return;                         // uniform per wave
   const int a = g.nptr[v], b = g.nptr[v + 1];
   double slog = 0.0, sco = 0.0;
-  for (int q = a; q < b; ++q) {
+  for (int q = a + lane; q < b; q += 64) {
     const int e = g.nedge[q];
     const double k = double(g.eptr[e + 1] - g.eptr[e]);
     slog += log(k);
     sco += k - 1.0;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    slog += __shfl_down(slog, o);
+    sco += __shfl_down(sco, o);
+  }
+  if (lane != 0) return;
   const double d = double(b - a);
   float f[KF] = {};
   f[0] = float(log1p(d));
@@ -684,7 +692,7 @@ int sttsv_mpnn_graph(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_
     }
   }
   if (good) {
-    hipLaunchKernelGGL(feat_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, g);
+    hipLaunchKernelGGL(feat_kernel, dim3((n + 3) / 4), dim3(256), 0, 0, g);
     hipLaunchKernelGGL(inv_size_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, 0, g);
     good = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
   }

@@ -61,11 +61,12 @@ def validate(eptr, eidx, n, r):
     return eptr, eidx
 
 
-def _edge_terms(M, x, r, k, chunk=1 << 15):
+def _edge_terms(M, x, r, k, chunk=1 << 15, members=None):
     """Terms of Alg. 2 for a block of edges of size k.
 
     M: (m_k, k) member ids.  Returns (m_k, k) FP64 terms, column p being the
-    term of member M[:, p]."""
+    term of member M[:, p].  ``members`` limits the work to those columns
+    (the others are left undefined)."""
     wk = weight_fp64(r, k)
     inv_fact = np.array([1.0 / math.factorial(a) for a in range(r)])
     out = np.empty(M.shape, dtype=np.float64)
@@ -81,7 +82,7 @@ def _edge_terms(M, x, r, k, chunk=1 << 15):
         Eb = E.copy()
         Eb[:, :, 0] = 0.0
         scale = s ** (r - 1)
-        for p in range(k):
+        for p in (range(k) if members is None else members):
             c = E[:, p, :].copy()                    # E_r(x_v)
             for q in range(k):
                 if q == p:
@@ -130,7 +131,13 @@ def sttsv(eptr, eidx, n, r, x):
 def sttsv_at(eptr, eidx, n, r, x, nodes):
     """y_v for a list of vertices only: each requested y_v is the fsum of
     the terms of the edges that contain v.  Used to check full-size runs on
-    sampled outputs."""
+    sampled outputs.
+
+    Only the requested members' terms are formed: each (edge, requested
+    member) pair becomes a row with that member first and the others after
+    it in their original order, and column 0 of that row is computed.  The
+    factors of a term are then multiplied in the same order as in ``sttsv``,
+    so every term, and every y_v, is bitwise the same as there."""
     eptr = np.asarray(eptr, dtype=np.int64)
     eidx = np.asarray(eidx, dtype=np.int64)
     x = np.asarray(x, dtype=np.float64)
@@ -142,10 +149,15 @@ def sttsv_at(eptr, eidx, n, r, x, nodes):
     sizes = np.diff(eptr)[hit]
     acc = {int(v): [] for v in nodes}
     for k in np.unique(sizes):
+        k = int(k)
         rows = hit[sizes == k]
         M = eidx[eptr[rows][:, None] + np.arange(k)[None, :]]
-        T = _edge_terms(M, x, r, int(k))
-        sel = want[M]
-        for v, t in zip(M[sel].tolist(), T[sel].tolist()):
+        er, ep = np.nonzero(want[M])                 # (edge row, member position) pairs
+        # column order per pair: the member itself, then the others in order
+        rest = np.arange(k)[None, :].repeat(len(ep), axis=0)
+        rest = rest[rest != ep[:, None]].reshape(len(ep), k - 1)
+        Mp = np.take_along_axis(M[er], np.concatenate([ep[:, None], rest], axis=1), axis=1)
+        T = _edge_terms(Mp, x, r, k, members=(0,))[:, 0]
+        for v, t in zip(Mp[:, 0].tolist(), T.tolist()):
             acc[v].append(t)
     return np.array([math.fsum(acc[int(v)]) for v in nodes])

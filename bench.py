@@ -80,8 +80,8 @@ def stage_work(stages, bucket_k, bucket_m, r):
     fused generic stages: the same summed over the buckets that no per-bucket
     stage covers and whose window is in the stage's range; the copy of x into
     degree-rank order: 4 B index + 8 B read + 8 B written per vertex;
-    reduction levels: per term the value read (8 B, plus its 4 B gather index
-    at level 0), per chunk its 12 B descriptor and the 8 B result."""
+    reduction levels: per term the value read (8 B, plus its 2 B LDS slot at
+    level 0), per chunk its 12 B descriptor and the 8 B result."""
     per_bucket = {s["size"] for s in stages if s["kind"] == 0}
     out = []
     for s in stages:
@@ -100,7 +100,7 @@ def stage_work(stages, bucket_k, bucket_m, r):
         elif s["kind"] == 3:
             out.append((0.0, 20.0 * s["count"], "x into degree-rank order, n=%d" % s["count"]))
         else:
-            per_term = 12.0 if s["size"] == 0 else 8.0
+            per_term = 10.0 if s["size"] == 0 else 8.0
             out.append((0.0, per_term * s["in_len"] + 20.0 * s["count"],
                         "reduce level %d, %d chunks" % (s["size"], s["count"])))
     return out
@@ -165,8 +165,8 @@ def stage_kernel(s, prec, r):
         return "edge_generic<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
     if s["kind"] == 2:
         if s["size"] == 0:
-            return "reduce_level0<true, false>", None
-        return "reduce_level<false, false>", s["count"] * 8
+            return "reduce_level0", None
+        return "reduce_level<false>", s["count"] * 8
     if s["kind"] == 3:
         return "permute_x", (s["count"] + 255) // 256 * 256
     return None, None

@@ -24,7 +24,10 @@ constexpr int kGenBlock = 64;            // threads per block of the generic ker
 constexpr int kSmallBlock = 256;         // threads per block of the other edge kernels
 constexpr int kChunk = 32;               // reduction chunk length (fixed: part of the format)
 constexpr int kXcd = 8;                  // accelerator dies (XCDs); workgroups go round-robin over them
-constexpr int kRegionTarget = 1 << 17;   // contributions per vertex block (1 MiB of FP64)
+constexpr int kStageTerms = 20480;       // contributions one level-0 workgroup stages in LDS (160 KiB, all of it)
+constexpr int kStageThreads = 1024;      // threads of a level-0 workgroup
+constexpr int kStagePasses = 16;         // passes over its chunks a level-0 workgroup makes (at most)
+constexpr int kStageRuns = kXcd;         // contiguous contribution ranges per level-0 workgroup (at most)
 constexpr int32_t kNoDst = INT32_MIN;    // padding chunk of the reduction schedule: no output
 constexpr int kRunMax = 4;               // prefix reuse: edges per run (per thread)
 constexpr int kGenRanges = 8;            // window ranges of the fused generic kernels
@@ -108,12 +111,21 @@ struct ReduceLevel {
   // kNoDst: padding), w = the same with the vertex's degree-rank position
   // in place of its id (the solver keeps its vectors in that order)
   int4* d_desc = nullptr;
-  // level 0: workgroup table {first chunk, lanes per chunk (8, 4, 2, 1),
-  // chunks, unused}; null for the other levels (8 lanes per chunk)
+  // level 0 only (null for the other levels, which use 8 lanes per chunk):
+  // two int4 per workgroup, {first chunk, chunks summed by 8 lanes, by 4,
+  // by 2} and {chunks summed by 1 lane, first range, ranges, 0}.  The
+  // workgroup's terms are consecutive node-major incidences; it copies its
+  // contribution ranges (int2 {first place, length}) into LDS, every term
+  // to its node-major offset (d_lpos, one per place), so each chunk is a
+  // run of LDS.  Its chunk descriptors are int2 {LDS offset | length << 16,
+  // destination}, with vertex ids [0] or degree-rank positions [1] as
+  // destinations.
   int4* d_wg = nullptr;
   int64_t nwg = 0;
+  int2* d_ranges = nullptr;
+  uint16_t* d_lpos = nullptr;
+  int2* d_desc0[2] = {nullptr, nullptr};
   int64_t in_len = 0;           // length of this level's input array
-  const int32_t* d_gather = nullptr;   // level 0: contribution index of each term
 };
 
 struct Bucket {
@@ -199,8 +211,14 @@ struct Plan {
   std::vector<int32_t> vblock;    // vertex block of every vertex
   std::vector<int64_t> region;    // first contribution index of every block (+ nnz at the end)
   int32_t* d_loc = nullptr;       // contribution index of every member slot
-  int32_t* d_glist = nullptr;     // contribution index of every node-major incidence
-  std::vector<int32_t> glist;     // host copy
+  std::vector<int32_t> glist;     // contribution index of every node-major incidence (host)
+  // level-0 schedule on the host: per workgroup {first chunk, 8-, 4-, 2-lane
+  // chunks}, its 1-lane chunk count and its first node-major incidence.  The
+  // LDS ranges and offsets follow from the places, so they are rebuilt
+  // whenever the places change.
+  std::vector<int4> l0_wg;
+  std::vector<int32_t> l0_n1;
+  std::vector<int64_t> l0_base, l0_terms;
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
   double* d_contrib = nullptr;    // contributions, one region per vertex block
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
@@ -237,7 +255,7 @@ void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t*
 void build_stages(Plan& p);   // fills p.stages from buckets, groups and levels
 int init_lanes(Plan& p);      // helper streams and events of the edge lanes
 int build_groups(Plan& p);    // (re)builds the fused generic groups (plan.cpp)
-int assign_places(Plan& p);   // contribution places for the current kernel choice (plan.cpp)
+int assign_places(Plan& p);   // contribution places (and the level-0 LDS slots) for the current kernel choice
 int set_reuse(Plan& p, Bucket& b, bool by_flag);   // prefix-reuse runs of a bucket (plan.cpp)
 // The edge launches of one precision (per-graph skip flags, nullable), and
 // the reduction alone: the solver runs both precisions' edge launches then

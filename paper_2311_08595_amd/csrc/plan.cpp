@@ -16,15 +16,16 @@
 //  7a. the edge kernels gather x in degree-rank order (hubs first, so the hot
 //     part of x shares cache lines): on the device, member slots hold rank
 //     positions voff + rank, and every STTSV first copies x into that order;
-//  8. contribution storage: vertices (in index order) form blocks of about
-//     kRegionTarget incidences; each block owns a contiguous region, split
-//     into one part per die (workgroup w of a launch runs on die w mod 8),
-//     and the incidences that one die's edge workgroups produce for the
-//     block take consecutive places in its part, in (bucket, edge, member)
-//     order.  The edge kernels' stores then advance a few thousand write
-//     fronts, each filled by one die's L2, instead of landing anywhere in
-//     the array, and the reduction of one block gathers from one L2-sized
-//     region.
+//  8. contribution storage: vertices (in index order) form blocks of at
+//     most kStageTerms incidences (a vertex with more forms a block of its
+//     own); each block owns a contiguous region, split into one part per die
+//     (workgroup w of a launch runs on die w mod 8), and the incidences that
+//     one die's edge workgroups produce for the block take consecutive
+//     places in its part, in (bucket, edge, member) order.  The edge
+//     kernels' stores then advance write fronts, each filled by one die's
+//     L2, instead of landing anywhere in the array, and a level-0 reduction
+//     workgroup copies one block's region (or, for a larger vertex, at most
+//     one range per die part) into LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,11 +39,9 @@
 namespace sttsv {
 namespace {
 
-// One level of the reduction schedule (host side); wg: level-0 workgroup
-// table {first chunk, lanes per chunk, chunks} (empty for other levels).
+// One level of the reduction schedule (host side).
 struct HostLevel {
   std::vector<int32_t> start, len, dst;
-  std::vector<int4> wg;
   int64_t in_len = 0;
 };
 
@@ -50,18 +49,36 @@ struct HostLevel {
 // chunks that fit (the kernel then adds the missing partial sums as the
 // zeros they are, so the tree and its bits do not change).
 int group_lanes(int32_t l) { return l <= 1 ? 1 : l == 2 ? 2 : l <= 4 ? 4 : 8; }
+int lane_class(int32_t l) { return group_lanes(l) == 8 ? 0 : group_lanes(l) == 4 ? 1 : group_lanes(l) == 2 ? 2 : 3; }
 
-// Launch order of reduction level 0.  Workgroup w (256 threads) takes
-// 256 / lanes consecutive chunks of one vertex block that all use the same
-// lane count, and is dispatched to die w mod kXcd.  Each die receives whole
-// vertex blocks (largest first, to the least-loaded die) and works through
-// them in turn, so the region it gathers from stays in its own L2; a block
-// heavier than half a die's share (a hub, whose terms are contiguous anyway)
-// is dealt over all dies.  Inside a block the chunks go longest first, so
-// the lanes of a wave do similar work.  Dies with fewer workgroups get empty
-// ones.
-HostLevel xcd_schedule(const HostLevel& L, const std::vector<int32_t>& cblock) {
-  constexpr int T = 256;
+// Level-0 chunks of a vertex of degree d, counted per lane class (8, 4, 2, 1).
+void add_chunks(int64_t d, int64_t cnt[4]) {
+  if (d <= kChunk) {
+    cnt[lane_class(static_cast<int32_t>(d))]++;
+    return;
+  }
+  const int64_t nch = (d + kChunk - 1) / kChunk;
+  cnt[0] += nch - 1;
+  cnt[lane_class(static_cast<int32_t>(d - (nch - 1) * kChunk))]++;
+}
+
+// Passes a level-0 workgroup makes over chunks counted per lane class.
+int64_t stage_passes(const int64_t cnt[4]) {
+  int64_t p = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t per = kStageThreads / (8 >> q);
+    p += (cnt[q] + per - 1) / per;
+  }
+  return p;
+}
+
+// Launch order of reduction level 0.  One workgroup per vertex block (at
+// most kStageTerms incidences and kStagePasses passes), and one per
+// kStageTerms / kChunk consecutive chunks of a larger vertex (its own
+// block); inside a workgroup the chunks go longest first, so they fall into
+// runs of equal lane counts (8, 4, 2, 1); workgroups go heaviest first.
+// Fills P.l0_* and returns the level with its chunks in that order.
+HostLevel level0_schedule(Plan& P, const HostLevel& L, const std::vector<int32_t>& cblock) {
   const int64_t nc = static_cast<int64_t>(L.len.size());
   int32_t nb = 0;
   for (int64_t c = 0; c < nc; ++c) nb = std::max(nb, cblock[c] + 1);
@@ -69,64 +86,91 @@ HostLevel xcd_schedule(const HostLevel& L, const std::vector<int32_t>& cblock) {
   for (int64_t c = 0; c < nc; ++c) bc[cblock[c]].push_back(c);
   struct Wg {
     int32_t block;
-    int64_t first;   // first chunk within the block's sorted list
-    int32_t count, lanes;
+    int64_t first, count, terms;   // chunks [first, first + count) of the block's list
   };
-  std::vector<std::vector<Wg>> bw(nb);
-  int64_t total = 0;
+  std::vector<Wg> wgs;
+  constexpr int64_t kPiece = kStageTerms / kChunk;
   for (int32_t b = 0; b < nb; ++b) {
-    auto& v = bc[b];
-    std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t q) { return L.len[a] > L.len[q]; });
-    for (size_t i = 0; i < v.size();) {
-      const int g = group_lanes(L.len[v[i]]);
-      size_t j = i;
-      while (j < v.size() && group_lanes(L.len[v[j]]) == g && j - i < static_cast<size_t>(T / g)) ++j;
-      bw[b].push_back(Wg{b, static_cast<int64_t>(i), static_cast<int32_t>(j - i), g});
-      i = j;
-    }
-    total += static_cast<int64_t>(bw[b].size());
-  }
-  std::vector<int32_t> order(nb);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t q) { return bw[a].size() > bw[q].size(); });
-  const int64_t big = std::max<int64_t>(1, total / (2 * kXcd));
-  std::vector<std::vector<Wg>> queue(kXcd);
-  auto least = [&]() {
-    int x = 0;
-    for (int y = 1; y < kXcd; ++y)
-      if (queue[y].size() < queue[x].size()) x = y;
-    return x;
-  };
-  for (int32_t b : order) {
-    if (static_cast<int64_t>(bw[b].size()) > big) {
-      for (const Wg& w : bw[b]) queue[least()].push_back(w);
-    } else {
-      const int x = least();
-      for (const Wg& w : bw[b]) queue[x].push_back(w);
+    const auto& v = bc[b];
+    const int64_t nv = static_cast<int64_t>(v.size());
+    const int64_t step = P.region[b + 1] - P.region[b] > kStageTerms ? kPiece : std::max<int64_t>(nv, 1);
+    for (int64_t i = 0; i < nv; i += step) {
+      const int64_t cnt = std::min(step, nv - i);
+      int64_t t = 0;
+      for (int64_t q = i; q < i + cnt; ++q) t += L.len[v[q]];
+      wgs.push_back(Wg{b, i, cnt, t});
     }
   }
-  size_t rounds = 0;
-  for (const auto& q : queue) rounds = std::max(rounds, q.size());
+  std::stable_sort(wgs.begin(), wgs.end(), [](const Wg& a, const Wg& q) { return a.terms > q.terms; });
   HostLevel R;
   R.in_len = L.in_len;
-  for (size_t t = 0; t < rounds; ++t)
-    for (int x = 0; x < kXcd; ++x) {
-      const int32_t c0 = static_cast<int32_t>(R.len.size());
-      if (t < queue[x].size()) {
-        const Wg& w = queue[x][t];
-        const auto& v = bc[w.block];
-        for (int64_t i = w.first; i < w.first + w.count; ++i) {
-          R.start.push_back(L.start[v[i]]);
-          R.len.push_back(L.len[v[i]]);
-          R.dst.push_back(L.dst[v[i]]);
-        }
-        R.wg.push_back(make_int4(c0, w.lanes, w.count, 0));
-      } else {
-        R.wg.push_back(make_int4(c0, 8, 0, 0));
-      }
+  P.l0_wg.clear();
+  P.l0_n1.clear();
+  P.l0_base.clear();
+  P.l0_terms.clear();
+  for (const Wg& w : wgs) {
+    std::vector<int64_t> v(bc[w.block].begin() + w.first, bc[w.block].begin() + w.first + w.count);
+    std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t q) { return L.len[a] > L.len[q]; });
+    int64_t cnt[4] = {0, 0, 0, 0};
+    int64_t base = INT64_MAX;
+    for (int64_t c : v) {
+      cnt[lane_class(L.len[c])]++;
+      if (L.len[c] > 0) base = std::min<int64_t>(base, L.start[c]);
     }
+    P.l0_wg.push_back(make_int4(static_cast<int32_t>(R.len.size()), static_cast<int32_t>(cnt[0]),
+                                static_cast<int32_t>(cnt[1]), static_cast<int32_t>(cnt[2])));
+    P.l0_n1.push_back(static_cast<int32_t>(cnt[3]));
+    P.l0_base.push_back(base == INT64_MAX ? 0 : base);
+    P.l0_terms.push_back(w.terms);
+    for (int64_t c : v) {
+      R.start.push_back(L.start[c]);
+      R.len.push_back(L.len[c]);
+      R.dst.push_back(L.dst[c]);
+    }
+  }
   return R;
+}
+
+// Level-0 LDS layout for the current places: the terms of a workgroup are
+// the node-major incidences [base, base + terms); it copies the maximal runs
+// of consecutive places they occupy (one run for a block of small vertices,
+// at most one per die part for a piece of a large vertex), each term to LDS
+// offset (its node-major index - base).
+int stage_level0(Plan& P) {
+  if (P.levels.empty() || P.levels[0].d_wg == nullptr) return STTSV_OK;
+  ReduceLevel& D = P.levels[0];
+  const size_t nwg = P.l0_wg.size();
+  std::vector<int4> wg(2 * nwg);
+  std::vector<int2> ranges;
+  std::vector<uint16_t> lpos(P.nnz, 0);
+  std::vector<int32_t> pl;
+  for (size_t w = 0; w < nwg; ++w) {
+    const int64_t base = P.l0_base[w], terms = P.l0_terms[w];
+    const int64_t cnt[4] = {P.l0_wg[w].y, P.l0_wg[w].z, P.l0_wg[w].w, P.l0_n1[w]};
+    if (terms > kStageTerms || base + terms > P.nnz || stage_passes(cnt) > kStagePasses) return STTSV_EINVAL;
+    pl.resize(terms);
+    for (int64_t q = 0; q < terms; ++q) {
+      pl[q] = P.glist[base + q];
+      lpos[pl[q]] = static_cast<uint16_t>(q);
+    }
+    std::sort(pl.begin(), pl.end());
+    const int32_t r0 = static_cast<int32_t>(ranges.size());
+    for (int64_t i = 0; i < terms; ++i) {
+      if (i > 0 && pl[i] == pl[i - 1]) return STTSV_EINVAL;   // two terms in one place
+      if (i == 0 || pl[i] != pl[i - 1] + 1) ranges.push_back(make_int2(pl[i], 0));
+      ranges.back().y++;
+    }
+    const int32_t nr = static_cast<int32_t>(ranges.size()) - r0;
+    if (nr > kStageRuns) return STTSV_EINVAL;
+    wg[2 * w] = P.l0_wg[w];
+    wg[2 * w + 1] = make_int4(P.l0_n1[w], r0, nr, 0);
+  }
+  if (hipMemcpy(D.d_wg, wg.data(), sizeof(int4) * wg.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (!ranges.empty() &&
+       hipMemcpy(D.d_ranges, ranges.data(), sizeof(int2) * ranges.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+      (P.nnz > 0 && hipMemcpy(D.d_lpos, lpos.data(), sizeof(uint16_t) * P.nnz, hipMemcpyHostToDevice) != hipSuccess))
+    return STTSV_EHIP;
+  return STTSV_OK;
 }
 
 struct Dsu {
@@ -216,7 +260,6 @@ void free_plan(Plan* p) {
   (void)hipFree(p->d_rid);
   (void)hipFree(p->d_xr);
   (void)hipFree(p->d_loc);
-  (void)hipFree(p->d_glist);
   (void)hipFree(p->d_gid);
   (void)hipFree(p->d_contrib);
   for (auto& g : p->groups) {
@@ -226,6 +269,10 @@ void free_plan(Plan* p) {
   for (auto& L : p->levels) {
     (void)hipFree(L.d_desc);
     (void)hipFree(L.d_wg);
+    (void)hipFree(L.d_ranges);
+    (void)hipFree(L.d_lpos);
+    (void)hipFree(L.d_desc0[0]);
+    (void)hipFree(L.d_desc0[1]);
   }
   for (double* d : p->d_partials) (void)hipFree(d);
   for (auto& b : p->buckets) {
@@ -512,11 +559,10 @@ int assign_places(Plan& P) {
   }
   std::vector<int32_t> glist(nnz);
   for (int64_t q = 0; q < nnz; ++q) glist[q] = loc[P.tslot[q]];
-  if (nnz > 0 && (hipMemcpy(P.d_loc, loc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess ||
-                  hipMemcpy(P.d_glist, glist.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess))
+  if (nnz > 0 && hipMemcpy(P.d_loc, loc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess)
     return STTSV_EHIP;
   P.glist = std::move(glist);
-  return STTSV_OK;
+  return stage_level0(P);
 }
 
 int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
@@ -655,14 +701,23 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     int64_t acc = 0;
     int32_t b = 0;
     P->region.assign(1, 0);
+    int64_t nv = 0;                   // vertices in the current block
+    int64_t cnt[4] = {0, 0, 0, 0};    // its level-0 chunks per lane class
     for (int32_t u = 0; u < n; ++u) {
-      if (acc > 0 && acc + deg[u] > kRegionTarget) {
+      int64_t with[4] = {cnt[0], cnt[1], cnt[2], cnt[3]};
+      add_chunks(deg[u], with);
+      if (nv > 0 && (acc + deg[u] > kStageTerms || stage_passes(with) > kStagePasses)) {
         P->region.push_back(P->region.back() + acc);
         ++b;
         acc = 0;
+        nv = 0;
+        for (int q = 0; q < 4; ++q) with[q] = 0;
+        add_chunks(deg[u], with);
       }
       vblock[u] = b;
       acc += deg[u];
+      ++nv;
+      for (int q = 0; q < 4; ++q) cnt[q] = with[q];
     }
     P->region.push_back(nnz);
   }
@@ -708,7 +763,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
         }
       }
       if (first) {
-        L = xcd_schedule(L, cblock);
+        L = level0_schedule(*P, L, cblock);
         first = false;
       }
       hl.push_back(std::move(L));
@@ -733,7 +788,6 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   for (int32_t q = 0; q < n; ++q) rpos[rid[q]] = q;
   if ((rc = upload<double>(&P->d_xr, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
-  if ((rc = upload<int32_t>(&P->d_glist, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
   for (size_t l = 0; l < hl.size(); ++l) {
@@ -742,18 +796,38 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     L.in_len = hl[l].in_len;
     P->levels.push_back(L);
     ReduceLevel& D = P->levels.back();
-    if (l == 0) D.d_gather = P->d_glist;
-    {
+    if (l > 0) {
       std::vector<int4> desc(D.nchunks);
       for (int64_t c = 0; c < D.nchunks; ++c) {
         const int32_t d = hl[l].dst[c];
         desc[c] = make_int4(hl[l].start[c], hl[l].len[c], d, d >= 0 ? rpos[d] : d);
       }
       if ((rc = upload(&D.d_desc, desc.data(), D.nchunks, &P->device_bytes)) != STTSV_OK) return fail(rc);
+    } else {
+      // packed level-0 descriptors: LDS offset within the workgroup's terms | length << 16
+      std::vector<int2> dv(D.nchunks), dr(D.nchunks);
+      for (size_t w = 0; w < P->l0_wg.size(); ++w) {
+        const int4 a = P->l0_wg[w];
+        const int64_t nch = (int64_t)a.y + a.z + a.w + P->l0_n1[w];
+        for (int64_t c = a.x; c < a.x + nch; ++c) {
+          const int64_t off = hl[0].len[c] > 0 ? hl[0].start[c] - P->l0_base[w] : 0;
+          if (off < 0 || off + hl[0].len[c] > P->l0_terms[w]) return fail(STTSV_EINVAL);
+          const int32_t x = static_cast<int32_t>(off | ((int64_t)hl[0].len[c] << 16));
+          const int32_t d = hl[0].dst[c];
+          dv[c] = make_int2(x, d);
+          dr[c] = make_int2(x, d >= 0 ? rpos[d] : d);
+        }
+      }
+      if ((rc = upload(&D.d_desc0[0], dv.data(), D.nchunks, &P->device_bytes)) != STTSV_OK ||
+          (rc = upload(&D.d_desc0[1], dr.data(), D.nchunks, &P->device_bytes)) != STTSV_OK)
+        return fail(rc);
     }
-    if (!hl[l].wg.empty()) {
-      D.nwg = static_cast<int64_t>(hl[l].wg.size());
-      if ((rc = upload(&D.d_wg, hl[l].wg.data(), hl[l].wg.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
+    if (l == 0 && !P->l0_wg.empty()) {
+      D.nwg = static_cast<int64_t>(P->l0_wg.size());
+      if ((rc = upload<int4>(&D.d_wg, nullptr, 2 * D.nwg, &P->device_bytes)) != STTSV_OK ||
+          (rc = upload<int2>(&D.d_ranges, nullptr, kStageRuns * D.nwg, &P->device_bytes)) != STTSV_OK ||
+          (rc = upload<uint16_t>(&D.d_lpos, nullptr, nnz, &P->device_bytes)) != STTSV_OK)
+        return fail(rc);
     }
     if (l + 1 < hl.size()) {
       double* part = nullptr;

@@ -1,9 +1,5 @@
 // Deterministic node-major reduction y_v = sum of v's per-incidence
 // contributions (replaces the AtomicAdd accumulation of Alg. 3 / Alg. 4).
-// Contributions live in one region per vertex block (about 1 MiB each, see
-// the planner); the first level gathers each vertex's terms from its block's
-// region, and its workgroups are ordered so that every die works through
-// its own blocks one at a time, keeping the gathered region in its L2.
 //
 // The summation tree of every vertex is fixed by its incidence list alone:
 // the list (canonical edge order) is cut into chunks of kChunk = 32
@@ -13,6 +9,16 @@
 // If a vertex has more than one chunk, the chunk sums are the input of the
 // next level and are cut the same way.  No launch parameter enters the tree,
 // so y is bitwise identical across runs, launch shapes and devices.
+//
+// The first level reads the contributions, which the edge kernels leave in
+// one contiguous region per block of vertices (at most kStageTerms of them
+// per block, or one vertex with more).  A level-0 workgroup owns one block,
+// or kStageTerms consecutive terms of a larger vertex, i.e. a run of
+// consecutive node-major incidences.  It copies its contributions into LDS
+// with coalesced loads, each term to its node-major offset, and then sums
+// every chunk from a run of LDS; the descriptors of all its passes are
+// loaded up front, so no pass waits for global memory.  Gathering straight
+// from global memory made every lane fetch its own cache line.
 #include "internal.hpp"
 
 namespace sttsv {
@@ -20,11 +26,14 @@ namespace {
 
 constexpr int kGroup = 8;                   // lanes per chunk
 constexpr int kPerLane = kChunk / kGroup;   // terms per lane
+constexpr int kCopyDepth = 4;                // loads in flight per thread while staging
 static_assert(kChunk % kGroup == 0, "chunk must split evenly over the group");
+static_assert(kStageTerms <= 65536, "LDS offsets are 16-bit");
+static_assert(kGroup == 8, "pass_at assumes lane classes 8, 4, 2, 1");
 
-template <bool GATHER, bool RANK>
+// Levels >= 1: chunk c of the level is summed by lanes 8c .. 8c+7.
+template <bool RANK>
 __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ desc, int64_t nchunks,
-                                                    const int32_t* __restrict__ gather,
                                                     const double* __restrict__ in,
                                                     double* __restrict__ y, double* __restrict__ next,
                                                     const int32_t* done) {
@@ -35,16 +44,12 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
   int4 dsc = make_int4(0, 0, kNoDst, 0);
   if (c < nchunks) dsc = desc[c];
   const int32_t s = dsc.x, l = dsc.y;
-  int32_t idx[kPerLane];
+  double v = 0.0;
 #pragma unroll
   for (int q = 0; q < kPerLane; ++q) {
     const int p = j + q * kGroup;
-    idx[q] = p < l ? (GATHER ? gather[s + p] : s + p) : -1;
+    if (p < l) v += in[s + p];
   }
-  double v = 0.0;
-#pragma unroll
-  for (int q = 0; q < kPerLane; ++q)
-    if (idx[q] >= 0) v += in[idx[q]];
   v += __shfl_down(v, 4, kGroup);
   v += __shfl_down(v, 2, kGroup);
   v += __shfl_down(v, 1, kGroup);
@@ -57,68 +62,104 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
   }
 }
 
-// A chunk of at most G < 8 terms summed by G lanes with the same tree: lane
-// j holds s_j (0.0 + t_j, or 0.0), and every partial sum the 8-lane tree
-// would take from an absent lane is added as the +0.0 it is.
-template <int G, bool GATHER>
-__device__ __forceinline__ double short_chunk(int4 d, int j, const int32_t* __restrict__ gather,
-                                              const double* __restrict__ in) {
-  double v = 0.0;
-  if (j < d.y) v += in[GATHER ? gather[d.x + j] : d.x + j];
-  v = v + 0.0;                                                    // + s_{j+4}
-  if constexpr (G >= 4) v += __shfl_down(v, 2, G); else v = v + 0.0;
-  if constexpr (G >= 2) v += __shfl_down(v, 1, G); else v = v + 0.0;
-  return v;
+// Copy src[0 .. len) into LDS, term i to st[pos[i]], kCopyDepth loads in
+// flight per thread.
+__device__ __forceinline__ void stage_range(const double* __restrict__ src, const uint16_t* __restrict__ pos,
+                                            double* st, int len) {
+  for (int i0 = 0; i0 < len; i0 += kStageThreads * kCopyDepth) {
+    double t[kCopyDepth];
+    int k[kCopyDepth];
+#pragma unroll
+    for (int u = 0; u < kCopyDepth; ++u) {
+      const int i = i0 + u * kStageThreads + static_cast<int>(threadIdx.x);
+      t[u] = i < len ? src[i] : 0.0;
+      k[u] = i < len ? static_cast<int>(pos[i]) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyDepth; ++u)
+      if (k[u] >= 0) st[k[u]] = t[u];
+  }
 }
 
-template <int G, bool GATHER, bool RANK>
-__device__ __forceinline__ void level0_group(const int4* __restrict__ desc, int4 w, const int32_t* __restrict__ gather,
-                                             const double* __restrict__ in, double* __restrict__ y,
-                                             double* __restrict__ next) {
-  const int lc = threadIdx.x / G, j = threadIdx.x % G;
-  const bool active = lc < w.z;                 // whole groups of G lanes agree
-  const int4 d = active ? desc[w.x + lc] : make_int4(0, 0, kNoDst, kNoDst);
-  double v;
-  if constexpr (G == kGroup) {
-    int32_t idx[kPerLane];
+// Pass p of a level-0 workgroup (uniform): lanes per chunk G (0: no such
+// pass), first chunk of the pass and end of its lane class.
+struct PassAt {
+  int G, lg, first, end;   // lg = log2 G
+};
+__device__ __forceinline__ PassAt pass_at(int p, int4 a, int n1) {
+  int c = a.x;
+  const int n[4] = {a.y, a.z, a.w, n1};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int G = kGroup >> q, per = kStageThreads / G;
+    const int np = (n[q] + per - 1) / per;
+    if (p < np) return PassAt{G, 3 - q, c + p * per, c + n[q]};
+    p -= np;
+    c += n[q];
+  }
+  return PassAt{0, 0, 0, 0};
+}
+
+// One pass: every group of G lanes sums one chunk from LDS.  G = 8: lane j
+// adds terms j, j+8, j+16, j+24, then the halving butterfly.  G < 8 (chunks
+// of at most G terms): lane j holds s_j = 0.0 + t_j (or 0.0), and every
+// partial sum the 8-lane tree would take from an absent lane is added as the
+// +0.0 it is, so the bits are those of the 8-lane tree.
+__device__ __forceinline__ void stage_pass(int G, int2 d, const double* st, double* __restrict__ y,
+                                           double* __restrict__ next) {
+  const int j = static_cast<int>(threadIdx.x) & (G - 1);
+  const int s = d.x & 0xffff, l = d.x >> 16;
+  double v = 0.0;
+  if (G == kGroup) {
 #pragma unroll
     for (int q = 0; q < kPerLane; ++q) {
       const int p = j + q * kGroup;
-      idx[q] = p < d.y ? (GATHER ? gather[d.x + p] : d.x + p) : -1;
+      if (p < l) v += st[s + p];
     }
-    v = 0.0;
-#pragma unroll
-    for (int q = 0; q < kPerLane; ++q)
-      if (idx[q] >= 0) v += in[idx[q]];
     v += __shfl_down(v, 4, kGroup);
     v += __shfl_down(v, 2, kGroup);
     v += __shfl_down(v, 1, kGroup);
   } else {
-    v = short_chunk<G, GATHER>(d, j, gather, in);
+    if (j < l) v += st[s + j];
+    v = v + 0.0;                                                    // + s_{j+4}
+    if (G >= 4) v += __shfl_down(v, 2, 4); else v = v + 0.0;
+    if (G >= 2) v += __shfl_down(v, 1, G); else v = v + 0.0;
   }
-  if (j == 0 && active) {
-    const int32_t t = RANK ? d.w : d.z;
-    if (t >= 0)
-      y[t] = v;
-    else if (t != kNoDst)
-      next[-(int64_t)t - 1] = v;
+  if (j == 0) {
+    if (d.y >= 0)
+      y[d.y] = v;
+    else if (d.y != kNoDst)
+      next[-(int64_t)d.y - 1] = v;
   }
 }
 
-// Level 0 with the workgroup table: workgroup b takes chunks
-// [wg[b].x, +wg[b].z), wg[b].y lanes each (uniform within the workgroup).
-template <bool GATHER, bool RANK>
-__global__ void __launch_bounds__(256) reduce_level0(const int4* __restrict__ desc, const int4* __restrict__ wg,
-                                                     const int32_t* __restrict__ gather,
-                                                     const double* __restrict__ in, double* __restrict__ y,
-                                                     double* __restrict__ next, const int32_t* done) {
+__global__ void __launch_bounds__(kStageThreads) reduce_level0(const int2* __restrict__ desc,
+                                                               const int4* __restrict__ wg,
+                                                               const int2* __restrict__ ranges,
+                                                               const uint16_t* __restrict__ lpos,
+                                                               const double* __restrict__ in,
+                                                               double* __restrict__ y, double* __restrict__ next,
+                                                               const int32_t* done) {
   if (done != nullptr && *done) return;
-  const int4 w = wg[blockIdx.x];
-  switch (w.y) {
-    case 1: level0_group<1, GATHER, RANK>(desc, w, gather, in, y, next); break;
-    case 2: level0_group<2, GATHER, RANK>(desc, w, gather, in, y, next); break;
-    case 4: level0_group<4, GATHER, RANK>(desc, w, gather, in, y, next); break;
-    default: level0_group<kGroup, GATHER, RANK>(desc, w, gather, in, y, next); break;
+  __shared__ double st[kStageTerms];
+  const int4 a = wg[2 * blockIdx.x], b = wg[2 * blockIdx.x + 1];
+  int2 d[kStagePasses];
+#pragma unroll
+  for (int p = 0; p < kStagePasses; ++p) {
+    const PassAt P = pass_at(p, a, b.x);
+    const int c = P.first + (static_cast<int>(threadIdx.x) >> P.lg);
+    d[p] = P.G > 0 && c < P.end ? desc[c] : make_int2(0, kNoDst);
+  }
+  for (int r = 0; r < b.z; ++r) {
+    const int2 rg = ranges[b.y + r];
+    stage_range(in + rg.x, lpos + rg.x, st, rg.y);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kStagePasses; ++p) {
+    const PassAt P = pass_at(p, a, b.x);
+    if (P.G == 0) break;
+    stage_pass(P.G, d[p], st, y, next);
   }
 }
 
@@ -128,35 +169,16 @@ hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y
                                const int32_t* done, hipStream_t s, bool rank_out) {
   if (L.nchunks == 0) return hipSuccess;
   if (L.d_wg != nullptr) {
-    const dim3 grid(static_cast<unsigned>(L.nwg));
-    const int4* d = L.d_desc;
-    const int4* w = L.d_wg;
-    if (L.d_gather != nullptr && rank_out)
-      hipLaunchKernelGGL((reduce_level0<true, true>), grid, dim3(256), 0, s, d, w, L.d_gather, in, y, next, done);
-    else if (L.d_gather != nullptr)
-      hipLaunchKernelGGL((reduce_level0<true, false>), grid, dim3(256), 0, s, d, w, L.d_gather, in, y, next, done);
-    else if (rank_out)
-      hipLaunchKernelGGL((reduce_level0<false, true>), grid, dim3(256), 0, s, d, w, nullptr, in, y, next, done);
-    else
-      hipLaunchKernelGGL((reduce_level0<false, false>), grid, dim3(256), 0, s, d, w, nullptr, in, y, next, done);
+    hipLaunchKernelGGL(reduce_level0, dim3(static_cast<unsigned>(L.nwg)), dim3(kStageThreads), 0, s,
+                       L.d_desc0[rank_out ? 1 : 0], L.d_wg, L.d_ranges, L.d_lpos, in, y, next, done);
     return hipGetLastError();
   }
   const int64_t threads = L.nchunks * kGroup;
   const dim3 grid(static_cast<unsigned>((threads + 255) / 256));
-  const int4* d = L.d_desc;
-  if (L.d_gather != nullptr) {
-    if (rank_out)
-      hipLaunchKernelGGL((reduce_level<true, true>), grid, dim3(256), 0, s, d, L.nchunks, L.d_gather, in, y, next, done);
-    else
-      hipLaunchKernelGGL((reduce_level<true, false>), grid, dim3(256), 0, s, d, L.nchunks, L.d_gather, in, y, next,
-                         done);
-  } else {
-    if (rank_out)
-      hipLaunchKernelGGL((reduce_level<false, true>), grid, dim3(256), 0, s, d, L.nchunks, nullptr, in, y, next, done);
-    else
-      hipLaunchKernelGGL((reduce_level<false, false>), grid, dim3(256), 0, s, d, L.nchunks, nullptr, in, y, next,
-                         done);
-  }
+  if (rank_out)
+    hipLaunchKernelGGL((reduce_level<true>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
+  else
+    hipLaunchKernelGGL((reduce_level<false>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
   return hipGetLastError();
 }
 

@@ -31,6 +31,18 @@ static_assert(kChunk % kGroup == 0, "chunk must split evenly over the group");
 static_assert(kStageTerms <= 65536, "LDS offsets are 16-bit");
 static_assert(kGroup == 8, "pass_at assumes lane classes 8, 4, 2, 1");
 
+// v from lane i + K of the same row of 16 lanes (DPP row shift; lanes whose
+// source lies outside the row get 0).  Chunk groups of 8, 4 and 2 lanes are
+// aligned within rows, and a lane only ever reads a lane of its own group
+// whose value the tree still needs.
+template <int K>
+__device__ __forceinline__ double lane_down(double v) {
+  static_assert(K >= 1 && K <= 15, "row shift");
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x100 + K, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x100 + K, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
 // Levels >= 1: chunk c of the level is summed by lanes 8c .. 8c+7.
 template <bool RANK>
 __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ desc, int64_t nchunks,
@@ -44,15 +56,18 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
   int4 dsc = make_int4(0, 0, kNoDst, 0);
   if (c < nchunks) dsc = desc[c];
   const int32_t s = dsc.x, l = dsc.y;
+  double t[kPerLane];
+#pragma unroll
+  for (int q = 0; q < kPerLane; ++q) {   // all loads first; an absent term re-reads the chunk's first
+    const int p = j + q * kGroup;
+    t[q] = in[p < l ? s + p : s];
+  }
   double v = 0.0;
 #pragma unroll
-  for (int q = 0; q < kPerLane; ++q) {
-    const int p = j + q * kGroup;
-    if (p < l) v += in[s + p];
-  }
-  v += __shfl_down(v, 4, kGroup);
-  v += __shfl_down(v, 2, kGroup);
-  v += __shfl_down(v, 1, kGroup);
+  for (int q = 0; q < kPerLane; ++q) v = j + q * kGroup < l ? v + t[q] : v;
+  v += lane_down<4>(v);
+  v += lane_down<2>(v);
+  v += lane_down<1>(v);
   if (j == 0 && c < nchunks) {
     const int32_t d = RANK ? dsc.w : dsc.z;
     if (d >= 0)
@@ -101,29 +116,32 @@ __device__ __forceinline__ PassAt pass_at(int p, int4 a, int n1) {
 }
 
 // One pass: every group of G lanes sums one chunk from LDS.  G = 8: lane j
-// adds terms j, j+8, j+16, j+24, then the halving butterfly.  G < 8 (chunks
-// of at most G terms): lane j holds s_j = 0.0 + t_j (or 0.0), and every
-// partial sum the 8-lane tree would take from an absent lane is added as the
-// +0.0 it is, so the bits are those of the 8-lane tree.
+// adds terms j, j+8, j+16, j+24 (the present ones, in that order), then the
+// halving butterfly.  G < 8 (chunks of at most G terms): lane j holds s_j =
+// 0.0 + t_j (or 0.0), and every partial sum the 8-lane tree would take from
+// an absent lane is added as the +0.0 it is, so the bits are those of the
+// 8-lane tree.  All LDS reads of a lane are issued before the first add
+// (indices clamped into the array; absent terms are not added).
 __device__ __forceinline__ void stage_pass(int G, int2 d, const double* st, double* __restrict__ y,
                                            double* __restrict__ next) {
   const int j = static_cast<int>(threadIdx.x) & (G - 1);
   const int s = d.x & 0xffff, l = d.x >> 16;
   double v = 0.0;
   if (G == kGroup) {
+    double t[kPerLane];
 #pragma unroll
-    for (int q = 0; q < kPerLane; ++q) {
-      const int p = j + q * kGroup;
-      if (p < l) v += st[s + p];
-    }
-    v += __shfl_down(v, 4, kGroup);
-    v += __shfl_down(v, 2, kGroup);
-    v += __shfl_down(v, 1, kGroup);
+    for (int q = 0; q < kPerLane; ++q) t[q] = st[min(s + j + q * kGroup, kStageTerms - 1)];
+#pragma unroll
+    for (int q = 0; q < kPerLane; ++q) v = j + q * kGroup < l ? v + t[q] : v;
+    v += lane_down<4>(v);
+    v += lane_down<2>(v);
+    v += lane_down<1>(v);
   } else {
-    if (j < l) v += st[s + j];
+    const double t = st[min(s + j, kStageTerms - 1)];
+    v = j < l ? v + t : v;
     v = v + 0.0;                                                    // + s_{j+4}
-    if (G >= 4) v += __shfl_down(v, 2, 4); else v = v + 0.0;
-    if (G >= 2) v += __shfl_down(v, 1, G); else v = v + 0.0;
+    if (G >= 4) v += lane_down<2>(v); else v = v + 0.0;
+    if (G >= 2) v += lane_down<1>(v); else v = v + 0.0;
   }
   if (j == 0) {
     if (d.y >= 0)

@@ -314,6 +314,7 @@ def main():
     ap.add_argument("--cpu-edges", type=int, default=300000)
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="time the plan as built, without autotuning")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
@@ -350,9 +351,8 @@ def main():
         del src, dst
 
     from paper_2311_08595_amd import _lib as L
-    res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist()}
-    for prec in ("fp64", "fp32"):
-        log("[bench] timing STTSV %s" % prec)
+
+    def time_apply(prec):
         for _ in range(a.warmup):
             plan.apply(xd, yd, precision=prec)
         torch.cuda.synchronize()
@@ -360,7 +360,24 @@ def main():
         for _ in range(a.steps):
             plan.apply(xd, yd, precision=prec)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / a.steps
+        return (time.perf_counter() - t0) / a.steps
+
+    # the plan as built, then autotuned once (kernel variants and stream
+    # lanes; both are setup like the plan itself and never change a bit of y)
+    untuned = {}
+    for prec in ("fp64", "fp32"):
+        log("[bench] timing STTSV %s (plan as built)" % prec)
+        untuned[prec] = time_apply(prec)
+    tune_s = None
+    if not a.no_tune:
+        t0 = time.perf_counter()
+        plan.autotune(xd, reps=5)
+        tune_s = time.perf_counter() - t0
+        log("[bench] autotuned in %.2f s" % tune_s)
+    res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist()}
+    for prec in ("fp64", "fp32"):
+        log("[bench] timing STTSV %s" % prec)
+        dt = time_apply(prec) if tune_s is not None else untuned[prec]
         stages = stage_table(plan, xd, yd, prec, a.stage_reps)
         # terms read by each reduction level: nnz at level 0, at most the previous
         # level's chunk count above it
@@ -392,7 +409,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "n": n, "m": m, "nnz": int(len(w["eidx"])), "r": r,
                    "sizes": "P(k)~k^-2.5 on [2,25]", "membership": "Zipf(1.0)",
-                   "parallelism": "1 GPU"},
+                   "parallelism": "1 GPU",
+                   "plan": "autotuned once before timing (kernel variants, stream lanes; bitwise-identical y)"
+                   if tune_s is not None else "as built"},
+        "untuned_ms_per_step": {"fp64": untuned["fp64"] * 1e3, "fp32": untuned["fp32"] * 1e3},
+        "autotune_s": tune_s,
     }
     from paper_2311_08595_amd import _lib
     bk, bm = res["bucket_k"], res["bucket_m"]

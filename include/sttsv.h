@@ -147,8 +147,9 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
  * sttsv_plan_autotune -- per size bucket and series type, time the kernel
  * variants that compute bitwise-identical contributions (register-resident
  * vs generic kernel for 4 <= |e| <= 7; suffix stack in LDS vs global memory
- * for the generic kernel) on the device and keep the fastest.  Tuning never
- * changes any bit of y.
+ * for the generic kernel) on the device and keep the fastest; then move the
+ * edge launches between the stream lanes while whole applies get faster.
+ * Tuning never changes any bit of y.
  *   x           device, double[n]: a representative input (e.g. the start
  *               vector of a solve); only read.
  *   reps        >= 1 timed launches per candidate (median taken).

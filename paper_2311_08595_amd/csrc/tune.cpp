@@ -2,8 +2,9 @@
 // that compute bitwise-identical contributions (so tuning never changes y):
 //   * 4 <= k <= 7: register-resident kernel vs the generic kernel;
 //   * generic buckets: suffix stack in LDS vs in global memory;
-//   * FP64 register-resident buckets: with or without prefix reuse.
-// Each candidate is launched alone on the plan's stream with the caller's x
+//   * FP64 register-resident buckets: with or without prefix reuse;
+// and then the stream lane of every edge launch (whole applies timed).
+// Each kernel candidate is launched alone on the plan's stream with the caller's x
 // and timed with hipEvents (median of reps); the choices are kept in the plan
 // and in a cache keyed by (series type, r, k, round(log2 m)), which can be
 // read from and appended to a text file.
@@ -115,6 +116,46 @@ float time_generic(Plan& p, Bucket& B, int t, bool lds, const EdgeCall& c, int r
   return ms;
 }
 
+// Stream lanes by measurement: starting from the cost-model assignment, move
+// one edge stage at a time to another lane and keep the move when the whole
+// apply (median of reps, hipEvents on the plan's stream) gets faster by more
+// than 0.5 %; repeat while a round finds a move (at most four rounds).  The
+// lanes never change any bit of y.
+int tune_lanes(Plan& p, const double* x, int reps) {
+  if ((p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr) return STTSV_OK;
+  double* y = nullptr;
+  if (hipMalloc(&y, sizeof(double) * static_cast<size_t>(p.n)) != hipSuccess) return STTSV_ENOMEM;
+  for (int seq = 0; seq < 2; ++seq) {
+    const int nl = p.lanes[seq];
+    if (nl < 2) continue;
+    const int prec = seq == 0 ? STTSV_PREC_FP64 : STTSV_PREC_FP32;
+    auto apply = [&] { return launch_sttsv(p, x, y, prec, nullptr, p.stream); };
+    float best = time_median(apply, reps, p.stream);
+    for (int round = 0; round < 4; ++round) {
+      bool moved = false;
+      for (Stage& S : p.stages[seq]) {
+        if (S.type != 0 && S.type != 1) continue;
+        const int from = S.lane;
+        for (int l = 0; l < nl; ++l) {
+          if (l == from || S.lane != from) continue;
+          S.lane = l;
+          const float t = time_median(apply, reps, p.stream);
+          if (t < 0.995f * best) {
+            best = t;
+            moved = true;
+          } else {
+            S.lane = from;
+          }
+        }
+      }
+      if (!moved) break;
+    }
+  }
+  const hipError_t e = hipStreamSynchronize(p.stream);
+  (void)hipFree(y);
+  return e == hipSuccess ? STTSV_OK : STTSV_EHIP;
+}
+
 }  // namespace
 
 int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t* tuned) {
@@ -189,6 +230,7 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
   if (rc == STTSV_OK) rc = assign_places(p);   // the die of an edge follows its kernel
   if (rc != STTSV_OK) return rc;
   build_stages(p);
+  if ((rc = tune_lanes(p, x, reps)) != STTSV_OK) return rc;
   if (tuned != nullptr) *tuned = count;
   return STTSV_OK;
 }

@@ -243,12 +243,16 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
     if ((e = launch_stage_call(p, S, c, nullptr, ls)) != hipSuccess) break;
   }
   if (nl > 1) {
-    // join (also after a failed launch, so no helper lane is left forked)
-    for (int l = 0; l < nl - 1; ++l) {
-      const hipError_t j = hipEventRecord(p.ev_join[l], p.aux[l]);
-      const hipError_t w = j == hipSuccess ? hipStreamWaitEvent(s, p.ev_join[l], 0) : j;
-      if (e == hipSuccess) e = w;
+    // join (also after a failed launch, so no helper lane is left forked):
+    // helper l waits for helper l-1, and the plan's stream waits for the
+    // last helper only, so only one cross-queue wait sits on its path
+    hipError_t w = hipSuccess;
+    for (int l = 0; l < nl - 1 && w == hipSuccess; ++l) {
+      if (l > 0) w = hipStreamWaitEvent(p.aux[l], p.ev_join[l - 1], 0);
+      if (w == hipSuccess) w = hipEventRecord(p.ev_join[l], p.aux[l]);
     }
+    if (w == hipSuccess) w = hipStreamWaitEvent(s, p.ev_join[nl - 2], 0);
+    if (e == hipSuccess) e = w;
   }
   return e;
 }

@@ -302,6 +302,53 @@ def bench_batch(a):
     return res
 
 
+def bench_paper_synthetic(a):
+    """The paper's synthetic sets S1-S4 (n=2500, m=25000, sizes 5, 10, ...,
+    N_k for N_k = 30, 40, 50, 60, r = N_k): FP64 STTSV by the memoised
+    kernels against the NAIVE algorithm (Alg. 3) on the same GPU and plan,
+    the shape of the paper's memoised-vs-naive comparison.  Work counts:
+    truncated products per edge k(k-1) (naive, Sec. IV) vs 2(k-3) windowed
+    ones (memoised); naive series FMAs k(k-1) r(r-1)/2 per edge."""
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import workloads as wl
+    rows = []
+    reps = max(5, min(a.steps, 20))
+    for nk in (30, 40, 50, 60):
+        d = wl.paper_synthetic(nk)
+        n, r = d["n"], d["r"]
+        sizes = np.diff(d["eptr"])
+        m = len(sizes)
+        with st.Plan(d["eptr"], d["eidx"], n, r) as p:
+            xd = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+            yd = torch.empty_like(xd)
+
+            def run(f):
+                for _ in range(3):
+                    f(xd, yd)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    f(xd, yd)
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t0) / reps
+            t_memo = run(lambda x, y: p.apply(x, y, precision="fp64"))
+            t_naive = run(p.apply_naive)
+        k = sizes.astype(np.float64)
+        naive_fma = float(np.sum(k * (k - 1)) * r * (r - 1) / 2)
+        memo_fma = float(sum(edge_fma(int(kk), r) * int(c) for kk, c in zip(*np.unique(sizes, return_counts=True))))
+        row = {"set": "S%d" % (nk // 10 - 2), "r": r, "m": m, "nnz": int(len(d["eidx"])),
+               "memoised_ms": t_memo * 1e3, "naive_ms": t_naive * 1e3, "speedup": t_naive / t_memo,
+               "memoised_hyperedges_per_s": m / t_memo, "naive_hyperedges_per_s": m / t_naive,
+               "products_naive": int(np.sum(sizes * (sizes - 1))),
+               "products_memoised": int(np.sum(np.where(sizes >= 4, 2 * (sizes - 3), (sizes == 3).astype(np.int64)))),
+               "naive_tflops": 2 * naive_fma / t_naive / 1e12, "memoised_tflops": 2 * memo_fma / t_memo / 1e12}
+        rows.append(row)
+        log("[bench]   %s (r=%d): memoised %.3f ms, naive %.3f ms (%.1fx), naive %.1f TFLOP/s"
+            % (row["set"], r, row["memoised_ms"], row["naive_ms"], row["speedup"], row["naive_tflops"]))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +361,7 @@ def main():
     ap.add_argument("--cpu-edges", type=int, default=300000)
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-synthetic", action="store_true", help="skip the S1-S4 memoised-vs-naive comparison")
     ap.add_argument("--no-tune", action="store_true", help="time the plan as built, without autotuning")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -534,6 +582,9 @@ def main():
             tgt["n1e6_plain_fp64_s"] = sv["fp64"]["seconds"]
             tgt["n1e6_met"] = sv["net_start_fp32_fp64"]["seconds"] < sv["fp64"]["seconds"]
         out["warm_start_target"] = tgt
+    if not a.no_synthetic:
+        log("[bench] paper synthetic sets S1-S4: memoised vs naive (Alg. 3)")
+        out["paper_synthetic"] = bench_paper_synthetic(a)
     if not a.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_edges)

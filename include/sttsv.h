@@ -144,6 +144,23 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
                       int64_t* counts, float* ms);
 
 /*
+ * sttsv_apply_naive -- y = B x^(r-1) by the paper's NAIVE algorithm (Alg. 3,
+ * complexity in Sec. IV): every (edge, member) pair multiplies out its own
+ * generating function e^{x_v t} prod_{u != v}(e^{x_u t} - 1) with full-length
+ * FP64 series (degrees 0..r-1), sharing nothing between members or edges:
+ * |e|(|e|-1) truncated products per edge.  A comparison baseline for the
+ * memoised kernels of sttsv_apply, not a faster path.
+ *   x, y   device double[n], as for sttsv_apply (y fully overwritten; x != y).
+ * Always FP64, whatever the plan's precision; the node reduction is the
+ * plan's deterministic one, so the result is bitwise reproducible but not
+ * bitwise equal to sttsv_apply's (the products round differently).
+ * Asynchronous on the plan's stream; it shares the plan's contribution
+ * buffer with sttsv_apply, so calls on one plan must not overlap.
+ * Errors: EINVAL (NULL plan, x or y, or x == y), EHIP (launch failure).
+ */
+int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y);
+
+/*
  * sttsv_plan_autotune -- per size bucket and series type, time the kernel
  * variants that compute bitwise-identical contributions (register-resident
  * vs generic kernel for 4 <= |e| <= 7; suffix stack in LDS vs global memory

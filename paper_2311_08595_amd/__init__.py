@@ -117,6 +117,17 @@ class Plan:
         _lib.check(self._lib.sttsv_apply_prec(self._h, xp, yp, prec))
         return y
 
+    def apply_naive(self, x, y=None):
+        """y = B x^(r-1) by Alg. 3 (no memoisation, FP64): the comparison
+        baseline for apply; returns y."""
+        import torch
+        xp = _dev_ptr(x, self.n, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        yp = _dev_ptr(y, self.n, "y")
+        _lib.check(self._lib.sttsv_apply_naive(self._h, xp, yp))
+        return y
+
     def solve(self, tol=1e-8, x0=None, out=None, max_iter=500, check_every=8, schedule="fp64",
               use_graph=True, shift=0.0, switch_tol=1e-6, raise_on_notconv=True):
         """NQZ iteration (Alg. 1).  Returns (x, info dict); x has l1 norm 1."""

@@ -34,7 +34,7 @@ Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, 
     Q_CONTRIB = range(11)
 
 # every symbol the header declares
-EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
+EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed", "sttsv_apply_naive",
            "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
            "sttsv_plan_graph_info", "sttsv_plan_autotune",
            "sttsv_mpnn_graph", "sttsv_mpnn_graph_destroy", "sttsv_mpnn_create", "sttsv_mpnn_destroy",
@@ -101,6 +101,7 @@ def load(path=None):
     lib.sttsv_plan.argtypes = [P, P, i64, i32, i32, ctypes.POINTER(SttsvOpts), ctypes.POINTER(P)]
     lib.sttsv_apply.argtypes = [P, P, P]
     lib.sttsv_apply_prec.argtypes = [P, P, P, i32]
+    lib.sttsv_apply_naive.argtypes = [P, P, P]
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]
     lib.heigvec_solve_ex.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo)]

@@ -36,6 +36,11 @@ int copy_out(const std::vector<S>& src, void* out, int64_t count) {
 
 }  // namespace
 
+// Alg. 3 baseline launch sequence (naive.hip)
+namespace sttsv {
+hipError_t launch_sttsv_naive(Plan& p, const double* x, double* y, hipStream_t s);
+}
+
 extern "C" {
 
 int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, int32_t r,
@@ -122,6 +127,16 @@ int sttsv_plan_autotune(sttsv_plan_t plan, const double* x, int32_t reps, const 
                         int32_t* tuned) {
   if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
   return guarded([&] { return sttsv::autotune(*plan->p, x, reps, cache_path, tuned); });
+}
+
+int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y) {
+  if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr) return STTSV_EINVAL;
+  if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
+  return guarded([&] {
+    Plan& p = *plan->p;
+    const hipError_t e = sttsv::launch_sttsv_naive(p, x, y, p.stream);
+    return e == hipSuccess ? STTSV_OK : STTSV_EHIP;
+  });
 }
 
 int sttsv_apply(sttsv_plan_t plan, const double* x, double* y) {

@@ -171,3 +171,22 @@ def warmstart_train_graph(i, n=10_000, base_seed=50_000):
     """Training graph i of the warm-start net: the Zipf/power-law recipe at
     n=1e4 (m=5e4, r=25)."""
     return zipf_powerlaw(seed=base_seed + i, n=n, m=5 * n)
+
+
+def paper_synthetic(nk, seed=None, n=2500, m=25000):
+    """The paper's synthetic sets S1-S4 (Sec. V, dataset table: n=2500,
+    m=25000, rank N_k = 30, 40, 50, 60): the union of 5-, 10-, ..., N_k-uniform
+    hypergraphs holding about the same number of edges each (m/(N_k/5), the
+    remainder spread one edge each over the first sizes), members uniform
+    without replacement; order r = N_k; x uniform on (0,1]."""
+    if nk % 5 != 0 or nk < 5:
+        raise ValueError("N_k must be a positive multiple of 5")
+    rng = np.random.default_rng(6000 + nk if seed is None else seed)
+    ks = np.arange(5, nk + 1, 5)
+    per = np.full(len(ks), m // len(ks))
+    per[: m - per.sum()] += 1
+    sizes = rng.permutation(np.repeat(ks, per))
+    eptr, eidx = uniform_members(rng, n, sizes)
+    x = uniform_x(rng, n)
+    return dict(eptr=eptr, eidx=eidx, n=n, r=nk, x=x, name=f"synthetic-S{nk // 10 - 2}-n{n}-m{m}-r{nk}")
+

@@ -79,5 +79,6 @@ def test_null_arguments():
     h = ctypes.c_void_p()
     assert lib.sttsv_plan(None, None, 1, 1, 2, None, ctypes.byref(h)) == _lib.STTSV_EINVAL
     assert lib.sttsv_apply(None, None, None) == _lib.STTSV_EINVAL
+    assert lib.sttsv_apply_naive(None, None, None) == _lib.STTSV_EINVAL
     assert lib.heigvec_solve(None, None, 1e-8, None, None) == _lib.STTSV_EINVAL
     assert lib.sttsv_plan_destroy(None) == _lib.STTSV_OK

@@ -78,3 +78,22 @@ def test_plan_reference_invariants():
         slots = p["tslot"][p["tptr"][v]:p["tptr"][v + 1]]
         assert np.all(p["mem"][slots] == v)
         assert len(slots) == deg[v]
+
+
+def test_paper_synthetic_recipe():
+    """S1-S4 (n=2500, m=25000, ranks 30..60): only multiples of 5 up to N_k,
+    equal edge counts per size (within one), no repeated member, r = N_k."""
+    for nk in (30, 40, 50, 60):
+        d = wl.paper_synthetic(nk)
+        sizes = np.diff(d["eptr"])
+        assert d["n"] == 2500 and len(sizes) == 25000 and d["r"] == nk
+        ks, counts = np.unique(sizes, return_counts=True)
+        assert list(ks) == list(range(5, nk + 1, 5))
+        assert counts.max() - counts.min() <= 1 and counts.sum() == 25000
+        for e in range(0, len(sizes), 997):
+            mem = d["eidx"][d["eptr"][e]:d["eptr"][e + 1]]
+            assert len(set(mem.tolist())) == len(mem)
+        assert d["eidx"].min() >= 0 and d["eidx"].max() < 2500
+        assert np.all(d["x"] > 0) and np.all(d["x"] <= 1)
+    a, b = wl.paper_synthetic(40), wl.paper_synthetic(40)
+    assert np.array_equal(a["eidx"], b["eidx"]) and np.array_equal(a["x"], b["x"])

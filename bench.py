@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-synthetic", action="store_true", help="skip the S1-S4 memoised-vs-naive comparison")
+    ap.add_argument("--synthetic-only", action="store_true",
+                    help="run only the S1-S4 memoised-vs-naive comparison (prints its rows as JSON)")
     ap.add_argument("--no-tune", action="store_true", help="time the plan as built, without autotuning")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -377,6 +379,10 @@ def main():
     from paper_2311_08595_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if a.synthetic_only:
+        log("[bench] paper synthetic sets S1-S4: memoised vs naive (Alg. 3)")
+        print(json.dumps({"paper_synthetic": bench_paper_synthetic(a)}), flush=True)
+        return
     log("[bench] generating workload")
     w = wl.zipf_powerlaw(n=a.n, m=a.m)
     n, r, m = w["n"], w["r"], len(w["eptr"]) - 1

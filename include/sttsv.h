@@ -161,6 +161,45 @@ int sttsv_apply_timed(sttsv_plan_t plan, const double* x, double* y, int32_t pre
 int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y);
 
 /*
+ * sttsv_contract -- the full contraction B x^r = x . (B x^(r-1)) (the
+ * quantity Sec. II's tensor defines on x^r; x^T y = B x^r).
+ *   x    device double[n]
+ *   y    device double[n], receives B x^(r-1) (FP64 series, as sttsv_apply_prec)
+ *   out  host double: B x^r, summed by a fixed-shape tree (reproducible bit for bit)
+ * Synchronous on the plan's stream.  Errors: EINVAL (NULL argument, x == y),
+ * ENOMEM, EHIP.
+ */
+int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out);
+
+typedef struct {
+    int32_t iterations;    /* updates of x performed                             */
+    int32_t converged;     /* 1 when the stopping rule was met                   */
+    double  lambda;        /* x . B x^(r-1) at the returned x                    */
+    double  residual;      /* ||B x^(r-1) - lambda x||_2 at the returned x       */
+} sttsv_zeig_info;
+
+/*
+ * zeigvec_sshopm -- a Z-eigenpair (B x^(r-1) = lambda x, ||x||_2 = 1) by the
+ * shifted power method that Sec. I names as an STTSV consumer (Kolda and
+ * Mayo's SS-HOPM, convex form): w = B x^(r-1) + alpha x, x <- w/||w||_2,
+ * lambda = x . B x^(r-1), until |lambda_k - lambda_(k-1)| <= tol |lambda_k|.
+ *   x0        device double[n] or NULL (all ones); normalised first; must not
+ *             be zero.  May equal x_out.
+ *   alpha     shift >= 0 (convex form)
+ *   tol       >= 0 (0: run max_iter updates)
+ *   max_iter  >= 0 updates of x
+ *   x_out     device double[n]: the last iterate (unit 2-norm)
+ *   info      host, nullable
+ * FP64 series whatever the plan's precision.  Synchronous; allocates its own
+ * device scratch (2 n + ~1600 doubles) for the call.  Errors: EINVAL (NULL plan
+ * or x_out, alpha < 0, tol < 0, max_iter < 0), ENUMERIC (zero or non-finite
+ * norm), ENOTCONV (max_iter reached: x_out and info hold the last iterate),
+ * ENOMEM, EHIP.
+ */
+int zeigvec_sshopm(sttsv_plan_t plan, const double* x0, double alpha, double tol, int32_t max_iter,
+                   double* x_out, sttsv_zeig_info* info);
+
+/*
  * sttsv_plan_autotune -- per size bucket and series type, time the kernel
  * variants that compute bitwise-identical contributions (register-resident
  * vs generic kernel for 4 <= |e| <= 7; suffix stack in LDS vs global memory

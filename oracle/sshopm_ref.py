@@ -21,6 +21,8 @@ Readings taken:
   magnitude with r and n).
 * One pass of the loop is one iteration; the returned pair is the last
   (x_{k+1}, lambda_{k+1}).  ``residual`` is ||y - lambda x||_2 there.
+* tol = 0 means "run max_iter updates" (no early stop even where lambda
+  repeats exactly), so runs can be compared iterate by iterate.
 
 Parity pins (tests/test_sshopm_oracle_pins.py): the graph case r = 2 gives the
 Perron eigenpair of the adjacency matrix; on a regular hypergraph the
@@ -65,7 +67,7 @@ def sshopm(eptr, eidx, n, r, x0, alpha=1.0, tol=1e-12, max_iter=500, history=Fal
         it += 1
         if history:
             hist.append((x.copy(), lam_new))
-        done = abs(lam_new - lam) <= tol * abs(lam_new)
+        done = tol > 0 and abs(lam_new - lam) <= tol * abs(lam_new)
         lam = lam_new
         if done:
             converged = True

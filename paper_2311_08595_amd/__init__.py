@@ -128,6 +128,33 @@ class Plan:
         _lib.check(self._lib.sttsv_apply_naive(self._h, xp, yp))
         return y
 
+    def contract(self, x, y=None):
+        """B x^r (full contraction); y receives B x^(r-1).  Returns (value, y)."""
+        import torch
+        xp = _dev_ptr(x, self.n, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        yp = _dev_ptr(y, self.n, "y")
+        out = ctypes.c_double()
+        _lib.check(self._lib.sttsv_contract(self._h, xp, yp, ctypes.byref(out)))
+        return out.value, y
+
+    def zeig_sshopm(self, x0=None, alpha=1.0, tol=1e-12, max_iter=500, out=None, raise_on_notconv=True):
+        """Z-eigenpair by the shifted power method (SS-HOPM, convex shift
+        alpha >= 0).  Returns (x, info dict); x has 2-norm 1."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        op = _dev_ptr(out, self.n, "out")
+        x0p = None if x0 is None else _dev_ptr(x0, self.n, "x0")
+        info = _lib.ZeigInfo()
+        rc = self._lib.zeigvec_sshopm(self._h, x0p, float(alpha), float(tol), int(max_iter), op,
+                                      ctypes.byref(info))
+        if rc != _lib.STTSV_OK and (rc != _lib.STTSV_ENOTCONV or raise_on_notconv):
+            _lib.check(rc)
+        return out, dict(iterations=info.iterations, converged=bool(info.converged), lambda_=info.lambda_,
+                         residual=info.residual, status=rc)
+
     def solve(self, tol=1e-8, x0=None, out=None, max_iter=500, check_every=8, schedule="fp64",
               use_graph=True, shift=0.0, switch_tol=1e-6, raise_on_notconv=True):
         """NQZ iteration (Alg. 1).  Returns (x, info dict); x has l1 norm 1."""

@@ -36,9 +36,12 @@ int copy_out(const std::vector<S>& src, void* out, int64_t count) {
 
 }  // namespace
 
-// Alg. 3 baseline launch sequence (naive.hip)
+// Alg. 3 baseline launch sequence (naive.hip); contraction and SS-HOPM (sshopm.hip)
 namespace sttsv {
 hipError_t launch_sttsv_naive(Plan& p, const double* x, double* y, hipStream_t s);
+int contract(Plan& p, const double* x, double* y, double* out);
+int zeig_sshopm(Plan& p, const double* x0, double alpha, double tol, int32_t max_iter, double* x,
+                sttsv_zeig_info* info);
 }
 
 extern "C" {
@@ -137,6 +140,19 @@ int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y) {
     const hipError_t e = sttsv::launch_sttsv_naive(p, x, y, p.stream);
     return e == hipSuccess ? STTSV_OK : STTSV_EHIP;
   });
+}
+
+int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out) {
+  if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr || out == nullptr) return STTSV_EINVAL;
+  if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
+  return guarded([&] { return sttsv::contract(*plan->p, x, y, out); });
+}
+
+int zeigvec_sshopm(sttsv_plan_t plan, const double* x0, double alpha, double tol, int32_t max_iter,
+                   double* x_out, sttsv_zeig_info* info) {
+  if (plan == nullptr || plan->p == nullptr || x_out == nullptr) return STTSV_EINVAL;
+  if (!(alpha >= 0.0) || !(tol >= 0.0) || max_iter < 0) return STTSV_EINVAL;
+  return guarded([&] { return sttsv::zeig_sshopm(*plan->p, x0, alpha, tol, max_iter, x_out, info); });
 }
 
 int sttsv_apply(sttsv_plan_t plan, const double* x, double* y) {

@@ -1,10 +1,12 @@
 """GPU parity of the full contraction and the shifted power method
 (``sttsv_contract``, ``zeigvec_sshopm``) against the CPU oracle.
 
-Tolerances: contraction and every iterate (x entries, lambda) 1e-12 relative
-(FP64 series; errors of a few ulps per step, all terms non-negative; entries
-of the unit iterate below 1e-200 absolutely); converged pairs: lambda 1e-10,
-x 1e-6 absolute on the unit vector (the two runs may stop one update apart).
+Tolerances: contraction, lambda at every iterate, and every entry of the
+first iterate 1e-12 relative (FP64 series, all terms non-negative; entries
+below 1e-200 absolutely); later iterates 1e-12 absolute on the unit vector
+(the map raises small entries to the power r-1, so their relative rounding
+differences grow like (r-1)^K while the iterates localise); converged pairs:
+lambda 1e-10, x 1e-6 absolute (the two runs may stop one update apart).
 """
 import sys
 
@@ -81,14 +83,24 @@ def test_sshopm_iterates_match_oracle(torch_cuda, name, seed, n, m, r, kmin, kma
     _, hist = sshopm_ref.sshopm(eptr, eidx, n, r, x0, alpha=alpha, tol=0.0, max_iter=12, history=True)
     with st.Plan(eptr, eidx, n, r) as plan:
         x0d = torch_cuda.tensor(x0, dtype=torch_cuda.float64, device="cuda")
-        for K in (0, 1, 5, 12):
+        for K in (0, 1, 3, 5, 12):
             xk, info = plan.zeig_sshopm(x0d, alpha=alpha, tol=0.0, max_iter=K, raise_on_notconv=False)
             xr, lr = hist["history"][K]
             xk = xk.cpu().numpy()
             assert info["iterations"] == K
-            _say(f"  K={K}: lambda rel err {abs(info['lambda_'] - lr) / lr:.2e}")
-            assert _close(xk, xr, 1e-12)
+            bad = np.abs(xk - xr) > 1e-12 * np.abs(xr) + 1e-200
+            _say(f"  K={K}: lambda rel err {abs(info['lambda_'] - lr) / lr:.2e}, "
+                 f"max abs err {np.max(np.abs(xk - xr)):.2e}, entries off {int(bad.sum())}"
+                 + (f" (e.g. {xk[bad][:3]} vs {xr[bad][:3]})" if bad.any() else ""))
             assert abs(info["lambda_"] - lr) <= 1e-12 * lr
+            if K <= 1:
+                assert not bad.any()
+            else:
+                # an entry fed mainly by (r-1)-th powers of other small entries
+                # carries r-1 times their relative error, so entrywise relative
+                # differences of rounding size grow like (r-1)^K on the small
+                # entries (the iterates localise); compare on the unit vector's scale
+                assert np.max(np.abs(xk - xr)) <= 1e-12
 
 
 def test_sshopm_converges_to_oracle_pair(torch_cuda):

@@ -568,6 +568,26 @@ def main():
                     log("[bench]   solve %s (learned start): %.4f s incl. %.4f s inference, %d iterations"
                         % (sched, solve["net_start_" + sched]["seconds"], infer,
                            solve["net_start_" + sched]["iterations"]))
+            try:   # a failure here must not cost the headline line
+                # another STTSV consumer: Z-eigenpair by the shifted power method
+                # (SS-HOPM), shift on the scale of B x^r at the unit start
+                x1 = torch.ones(n2, dtype=torch.float64, device="cuda")
+                x1 /= float(np.sqrt(n2))
+                lam0, _ = p2.contract(x1)
+                p2.zeig_sshopm(None, alpha=lam0, tol=1e-10, max_iter=300, raise_on_notconv=False)   # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, zi = p2.zeig_sshopm(None, alpha=lam0, tol=1e-10, max_iter=300, raise_on_notconv=False)
+                dt = time.perf_counter() - t0
+                solve["sshopm_fp64"] = dict(seconds=dt, iterations=zi["iterations"], converged=zi["converged"],
+                                            lambda_=zi["lambda_"], residual=zi["residual"], alpha=lam0,
+                                            ms_per_update=dt * 1e3 / max(zi["iterations"], 1))
+                log("[bench]   SS-HOPM Z-eigenpair: %.4f s, %d updates (%.3f ms each), residual/lambda %.1e"
+                    % (dt, zi["iterations"], dt * 1e3 / max(zi["iterations"], 1),
+                       zi["residual"] / zi["lambda_"] if zi["lambda_"] else float("nan")))
+            except Exception as exc:
+                solve["sshopm_fp64"] = {"error": str(exc)}
+                log("[bench]   SS-HOPM failed: %s" % exc)
         out["solve"] = solve
     if not a.no_batch:
         out["batched"] = bench_batch(a)

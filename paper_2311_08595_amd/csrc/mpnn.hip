@@ -210,14 +210,16 @@ __global__ void __launch_bounds__(256) dense_bwd_dx(const uint16_t* __restrict__
     }
 }
 
-// Ed_e = (1/|e|) sum_{v in e} H_v  (one wave per edge, lane = feature)
+// Ed_e = (1/|e|) sum_{v in e} H_v.  16 lanes per edge, 4 features per lane
+// (one 16-byte load per lane and row: a wave gathers 4 rows at once).
 __global__ void __launch_bounds__(256) edge_mean(Graph g, const float* __restrict__ Hh, float* __restrict__ E) {
-  const int64_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
+  const int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+  const int c = 4 * (threadIdx.x & 15);
   if (e >= g.m) return;
-  float acc = 0.f;
-  for (int q = g.eptr[e]; q < g.eptr[e + 1]; ++q) acc += Hh[(int64_t)g.eidx[q] * HD + c];
-  E[e * HD + c] = acc * g.inv_size[e];
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
+  for (int q = g.eptr[e]; q < g.eptr[e + 1]; ++q)
+    acc += *reinterpret_cast<const float4_t*>(Hh + (int64_t)g.eidx[q] * HD + c);
+  *reinterpret_cast<float4_t*>(E + e * HD + c) = acc * g.inv_size[e];
 }
 
 // Vertex-side sums over E(v), one wave per chunk of at most kVChunk terms,
@@ -233,39 +235,48 @@ __global__ void __launch_bounds__(256) vsum_level(int nchunk, const int32_t* __r
                                                   const float* __restrict__ inv_deg, const float* __restrict__ src,
                                                   const float* __restrict__ prev, float* __restrict__ part,
                                                   uint16_t* __restrict__ X, float* __restrict__ dH) {
-  const int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int f = threadIdx.x & 63;
+  // 16 lanes per chunk, 4 features per lane
+  const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+  const int f = 4 * (threadIdx.x & 15);
   if (c >= nchunk) return;
   const int32_t st = cstart[c], ln = clen[c], d = cdst[c];
-  float acc = 0.f;
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
   if (prev == nullptr) {
     for (int q = 0; q < ln; ++q) {
       const int e = nedge[st + q];
-      acc += MODE == 0 ? src[(int64_t)e * HD + f] : src[(int64_t)e * HD + f] * inv_size[e];
+      const float4_t t = *reinterpret_cast<const float4_t*>(src + (int64_t)e * HD + f);
+      if (MODE == 0)
+        acc += t;
+      else
+        acc += t * inv_size[e];
     }
   } else {
-    for (int q = 0; q < ln; ++q) acc += prev[(int64_t)(st + q) * HD + f];
+    for (int q = 0; q < ln; ++q) acc += *reinterpret_cast<const float4_t*>(prev + (int64_t)(st + q) * HD + f);
   }
   if (d < 0) {
-    part[(int64_t)(-(int64_t)d - 1) * HD + f] = acc;
+    *reinterpret_cast<float4_t*>(part + (int64_t)(-(int64_t)d - 1) * HD + f) = acc;
   } else if (MODE == 0) {
-    X[(int64_t)d * 2 * HD + HD + f] = to_bf16(acc * inv_deg[d]);
+    const float id = inv_deg[d];
+    uint16_t* xo = X + (int64_t)d * 2 * HD + HD + f;
+    for (int j = 0; j < 4; ++j) xo[j] = to_bf16(acc[j] * id);
   } else {
-    dH[(int64_t)d * HD + f] += acc;
+    float4_t* o = reinterpret_cast<float4_t*>(dH + (int64_t)d * HD + f);
+    *o = *o + acc;
   }
 }
 
-// adjoint of node_mean: dE_e = sum_{v in e} dA_v / d_v
+// adjoint of node_mean: dE_e = sum_{v in e} dA_v / d_v (16 lanes per edge,
+// 4 features per lane)
 __global__ void __launch_bounds__(256) node_mean_T(Graph g, const float* __restrict__ dA, float* __restrict__ dE) {
-  const int64_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
+  const int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+  const int c = 4 * (threadIdx.x & 15);
   if (e >= g.m) return;
-  float acc = 0.f;
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
   for (int q = g.eptr[e]; q < g.eptr[e + 1]; ++q) {
     const int v = g.eidx[q];
-    acc += dA[(int64_t)v * HD + c] * g.inv_deg[v];
+    acc += *reinterpret_cast<const float4_t*>(dA + (int64_t)v * HD + c) * g.inv_deg[v];
   }
-  dE[e * HD + c] = acc;
+  *reinterpret_cast<float4_t*>(dE + e * HD + c) = acc;
 }
 
 // s_v = H2_v . wout + bout  (one wave per vertex)
@@ -516,7 +527,7 @@ void vertex_sums(Net& N, const Graph& g, const float* src, uint16_t* X, float* d
   for (int l = 0; l < g.nlev; ++l) {
     const float* prev = l == 0 ? nullptr : N.vpart[(l - 1) & 1];
     float* part = N.vpart[l & 1];
-    hipLaunchKernelGGL((vsum_level<MODE>), dim3((g.nchunk[l] + 3) / 4), dim3(256), 0, s, g.nchunk[l],
+    hipLaunchKernelGGL((vsum_level<MODE>), dim3((g.nchunk[l] + 15) / 16), dim3(256), 0, s, g.nchunk[l],
                        (const int32_t*)g.cstart[l], (const int32_t*)g.clen[l], (const int32_t*)g.cdst[l],
                        (const int32_t*)g.nedge, (const float*)g.inv_size, (const float*)g.inv_deg, src, prev, part, X,
                        dH);
@@ -536,7 +547,7 @@ int forward(Net& N, const Graph& g, hipStream_t s) {
   int rc = ensure_workspace(N, g);
   if (rc == STTSV_OK) rc = ensure_vpart(N, g);
   if (rc != STTSV_OK) return rc;
-  const dim3 gd((g.n + 63) / 64), ge((g.m + 3) / 4), gv((g.n + 3) / 4);
+  const dim3 gd((g.n + 63) / 64), ge((g.m + 15) / 16), gv((g.n + 3) / 4);
   hipLaunchKernelGGL((dense_fwd<KF>), gd, dim3(256), 0, s, g.X0, KF, N.wt[0], N.p + OFF_B0, g.n, N.Z[0], N.Hh[0],
                      N.X[1]);
   for (int l = 1; l <= 2; ++l) {
@@ -563,7 +574,7 @@ int loss_and_grad(Net& N, const Graph& g, const double* xstar, float* loss_host,
   hipLaunchKernelGGL(outgrad_tile, dim3(tiles), dim3(256), 0, s, (const float*)N.Hh[2], (const float*)N.ds, g.n,
                      N.part);
   hipLaunchKernelGGL(sum_tiles, dim3(1), dim3(256), 0, s, (const float*)N.part, tiles, HD + 1, HD + 1, N.g + OFF_WO);
-  const dim3 gd((g.n + 63) / 64), ge((g.m + 3) / 4), gv((g.n + 3) / 4);
+  const dim3 gd((g.n + 63) / 64), ge((g.m + 15) / 16), gv((g.n + 3) / 4);
   const int64_t cnt = (int64_t)g.n * HD;
   const dim3 gc((unsigned)((cnt + 255) / 256));
   hipLaunchKernelGGL(score_bwd, gv, dim3(256), 0, s, (const float*)N.ds, (const float*)N.p, g.n, N.dH);

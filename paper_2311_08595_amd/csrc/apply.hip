@@ -224,11 +224,15 @@ int init_lanes(Plan& p) {
   return STTSV_OK;
 }
 
-hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s, XOrder order) {
-  const EdgeCall c{order == XOrder::kRank ? x : p.d_xr, p.d_contrib, done, gskip};
-  const int seq = precision == STTSV_PREC_FP32 ? 1 : 0;
-  const int nl = (p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr ? 1 : p.lanes[seq];
+// Edge stages of np precisions (precs[i] with per-graph skip flags skips[i])
+// inside one fork/join of the stream lanes.
+static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, const int32_t* const* skips, int np,
+                                   const int32_t* done, hipStream_t s, XOrder order) {
+  const double* xr = order == XOrder::kRank ? x : p.d_xr;
+  const bool multi = !(p.flags & STTSV_FLAG_ONE_STREAM) && p.ev_fork != nullptr;
+  int nl = 1;
+  if (multi)
+    for (int i = 0; i < np; ++i) nl = std::max(nl, p.lanes[precs[i] == STTSV_PREC_FP32 ? 1 : 0]);
   hipError_t e = order == XOrder::kVertex ? launch_permute(p, x, done, s) : hipSuccess;
   if (e != hipSuccess) return e;
   if (nl > 1) {
@@ -237,10 +241,15 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
     for (int l = 0; l < nl - 1; ++l)
       if ((e = hipStreamWaitEvent(p.aux[l], p.ev_fork, 0)) != hipSuccess) return e;
   }
-  for (const Stage& S : p.stages[seq]) {
-    if (S.type == 2 || S.type == 3) continue;
-    const hipStream_t ls = nl > 1 && S.lane > 0 ? p.aux[S.lane - 1] : s;
-    if ((e = launch_stage_call(p, S, c, nullptr, ls)) != hipSuccess) break;
+  for (int i = 0; i < np && e == hipSuccess; ++i) {
+    const int seq = precs[i] == STTSV_PREC_FP32 ? 1 : 0;
+    const bool lanes = nl > 1 && p.lanes[seq] > 1;
+    const EdgeCall c{xr, p.d_contrib, done, skips[i]};
+    for (const Stage& S : p.stages[seq]) {
+      if (S.type == 2 || S.type == 3) continue;
+      const hipStream_t ls = lanes && S.lane > 0 ? p.aux[S.lane - 1] : s;
+      if ((e = launch_stage_call(p, S, c, nullptr, ls)) != hipSuccess) break;
+    }
   }
   if (nl > 1) {
     // join (also after a failed launch, so no helper lane is left forked):
@@ -255,6 +264,18 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
     if (e == hipSuccess) e = w;
   }
   return e;
+}
+
+hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
+                        hipStream_t s, XOrder order) {
+  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order);
+}
+
+hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
+                             const int32_t* skip64, hipStream_t s) {
+  const int precs[2] = {STTSV_PREC_FP32, STTSV_PREC_FP64};
+  const int32_t* skips[2] = {skip32, skip64};
+  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank);
 }
 
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out) {

@@ -267,6 +267,11 @@ enum class XOrder { kVertex, kRank, kCopied };
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
                         hipStream_t s, XOrder order = XOrder::kVertex);
 // rank_out: write y in degree-rank order instead of vertex order.
+// FP32- and FP64-series edge stages (x already in rank order) inside one
+// fork/join, each gated by its own per-graph skip flags: the solver's mixed
+// schedule, where each graph runs one of the two per iteration.
+hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
+                             const int32_t* skip64, hipStream_t s);
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false);
 
 // reduction kernels (reduce.hip)

@@ -312,8 +312,10 @@ hipError_t enqueue_iteration(Plan& p, Solver& S, int schedule) {
   hipError_t e;
   const int32_t* all_done = &S.sctrl->all_done;
   if (schedule == STTSV_SOLVE_FP32_FP64)
-    if ((e = launch_edges(p, S.x, STTSV_PREC_FP32, all_done, S.skip32, S.s, XOrder::kRank)) != hipSuccess) return e;
-  if ((e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s, XOrder::kRank)) != hipSuccess) return e;
+    e = launch_edges_both(p, S.x, all_done, S.skip32, S.skip64, S.s);
+  else
+    e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s, XOrder::kRank);
+  if (e != hipSuccess) return e;
   if ((e = launch_reduction(p, S.z, all_done, S.s, true)) != hipSuccess) return e;
   hipLaunchKernelGGL((nqz_stats<true>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<true>), dim3(S.G), dim3(kRedBlock), 0, S.s, S);

@@ -233,7 +233,7 @@ typedef struct {
     int32_t schedule;      /* STTSV_SOLVE_* (default FP64)                       */
     int32_t use_graph;     /* 1 (default): replay a captured hipGraph           */
     double  shift;         /* alpha >= 0: z <- z + alpha x^[r-1] (default 0)    */
-    double  switch_tol;    /* FP32->FP64 switch threshold (default 1e-6)        */
+    double  switch_tol;    /* FP32->FP64 switch threshold (default 1e-4)        */
 } sttsv_solve_opts;
 
 typedef struct {

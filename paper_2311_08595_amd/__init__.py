@@ -89,7 +89,7 @@ class Plan:
         return dict(m=gi.m, n=gi.n, r=gi.r, voff=gi.voff, connected=bool(gi.connected))
 
     def solve_batch(self, tol=1e-8, x0=None, out=None, max_iter=500, check_every=8, schedule="fp64",
-                    use_graph=True, shift=0.0, switch_tol=1e-6, raise_on_notconv=True):
+                    use_graph=True, shift=0.0, switch_tol=1e-4, raise_on_notconv=True):
         """Alg. 1 for every graph of the plan at once.  Returns (x, [info per graph])."""
         import torch
         if out is None:
@@ -156,7 +156,7 @@ class Plan:
                          residual=info.residual, status=rc)
 
     def solve(self, tol=1e-8, x0=None, out=None, max_iter=500, check_every=8, schedule="fp64",
-              use_graph=True, shift=0.0, switch_tol=1e-6, raise_on_notconv=True):
+              use_graph=True, shift=0.0, switch_tol=1e-4, raise_on_notconv=True):
         """NQZ iteration (Alg. 1).  Returns (x, info dict); x has l1 norm 1."""
         import torch
         if out is None:

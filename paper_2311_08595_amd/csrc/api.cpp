@@ -169,7 +169,7 @@ int heigvec_solve_ex(sttsv_plan_t plan, const double* x0, double tol, const stts
   o.schedule = STTSV_SOLVE_FP64;
   o.use_graph = 1;
   o.shift = 0.0;
-  o.switch_tol = 1e-6;
+  o.switch_tol = 1e-4;
   if (opts != nullptr) o = *opts;
   if (plan->p->graphs.size() != 1) return STTSV_EINVAL;   // batches: heigvec_solve_batch
   return guarded([&] { return sttsv::solve(*plan->p, x0, tol, o, x_out, info); });
@@ -184,7 +184,7 @@ int heigvec_solve_batch(sttsv_plan_t plan, const double* x0, double tol, const s
   o.schedule = STTSV_SOLVE_FP64;
   o.use_graph = 1;
   o.shift = 0.0;
-  o.switch_tol = 1e-6;
+  o.switch_tol = 1e-4;
   if (opts != nullptr) o = *opts;
   return guarded([&] { return sttsv::solve(*plan->p, x0, tol, o, x_out, infos); });
 }

@@ -166,8 +166,9 @@ int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y);
  *   x    device double[n]
  *   y    device double[n], receives B x^(r-1) (FP64 series, as sttsv_apply_prec)
  *   out  host double: B x^r, summed by a fixed-shape tree (reproducible bit for bit)
- * Synchronous on the plan's stream.  Errors: EINVAL (NULL argument, x == y),
- * ENOMEM, EHIP.
+ * Synchronous on the plan's stream; allocates ~1.6k doubles of device scratch
+ * for the call.  On a batched plan the contraction is over the disjoint union.
+ * Errors: EINVAL (NULL argument, x == y), ENOMEM, EHIP.
  */
 int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out);
 
@@ -190,6 +191,7 @@ typedef struct {
  *   max_iter  >= 0 updates of x
  *   x_out     device double[n]: the last iterate (unit 2-norm)
  *   info      host, nullable
+ * On a batched plan the tensor is that of the disjoint union of its graphs.
  * FP64 series whatever the plan's precision.  Synchronous; allocates its own
  * device scratch (2 n + ~1600 doubles) for the call.  Errors: EINVAL (NULL plan
  * or x_out, alpha < 0, tol < 0, max_iter < 0), ENUMERIC (zero or non-finite

@@ -52,16 +52,17 @@ def beta_tuples(edge, r: int):
     return [t for t in product(e, repeat=r) if set(t) == es]
 
 
-def blowup_entries(edges, r: int) -> dict:
+def blowup_entries(edges, r: int, weights=None) -> dict:
     """Every non-zero of the order-r blowup tensor, listed one by one:
     {index tuple: Fraction}.  Distinct edges give disjoint beta(e); a repeated
-    edge (multiset input) adds its value again."""
+    edge (multiset input) adds its value again.  ``weights``: w(e) per edge
+    (exact numbers, e.g. Fractions of FP64 values), default w(e) = |e|."""
     B = {}
-    for e in edges:
+    for q, e in enumerate(edges):
         k = len(e)
         if k > r:
             raise ValueError("edge larger than the tensor order")
-        val = blowup_value(r, k)
+        val = blowup_value(r, k, None if weights is None else Fraction(weights[q]))
         for t in beta_tuples(e, r):
             B[t] = B.get(t, Fraction(0)) + val
     return B

@@ -36,9 +36,9 @@ import numpy as np
 from .sttsv_ref import sttsv
 
 
-def contract(eptr, eidx, n, r, x):
+def contract(eptr, eidx, n, r, x, w=None):
     """B x^r = sum_v x_v (B x^(r-1))_v, summed with math.fsum."""
-    y = sttsv(eptr, eidx, n, r, x)
+    y = sttsv(eptr, eidx, n, r, x, w)
     return math.fsum((np.asarray(x, dtype=np.float64) * y).tolist())
 
 

@@ -18,7 +18,10 @@ Two choices that change no value beyond rounding:
 * the terms of a vertex are summed with math.fsum (correctly rounded sum).
 
 The weight w(e)/|beta(e)| * (r-1)! is formed from exact integers and rounded
-to FP64 once.
+to FP64 once.  Edge weights other than the paper's w(e) = |e| (the hypergraph
+H = (V, E, w) of Sec. II is edge-weighted, and Alg. 2 takes w as input) are
+passed as one positive FP64 value per input edge; the weight factor is then
+formed exactly from that value and rounded once.
 """
 import math
 from fractions import Fraction
@@ -36,6 +39,23 @@ def weight_exact(r: int, k: int) -> Fraction:
 def weight_fp64(r: int, k: int) -> float:
     w = weight_exact(r, k)
     return w.numerator / w.denominator  # int/int true division rounds once
+
+
+def edge_weight_fp64(r: int, k: int, w: float) -> float:
+    """w(e)/|beta(e)| * (r-1)! for an edge of size k with weight w (an FP64
+    value), formed exactly and rounded once."""
+    f = Fraction(w) * Fraction(math.factorial(r - 1), beta_size(r, k))
+    return f.numerator / f.denominator
+
+
+def validate_weights(w, m):
+    """Edge weights: one finite, positive FP64 value per edge (or None)."""
+    if w is None:
+        return None
+    w = np.asarray(w, dtype=np.float64)
+    if w.shape != (m,) or not np.all(np.isfinite(w)) or np.any(w <= 0):
+        raise ValueError("edge weights must be m finite positive values")
+    return w
 
 
 def validate(eptr, eidx, n, r):
@@ -61,12 +81,13 @@ def validate(eptr, eidx, n, r):
     return eptr, eidx
 
 
-def _edge_terms(M, x, r, k, chunk=1 << 15, members=None):
+def _edge_terms(M, x, r, k, chunk=1 << 15, members=None, wts=None):
     """Terms of Alg. 2 for a block of edges of size k.
 
     M: (m_k, k) member ids.  Returns (m_k, k) FP64 terms, column p being the
     term of member M[:, p].  ``members`` limits the work to those columns
-    (the others are left undefined)."""
+    (the others are left undefined).  ``wts``: per-row weight factors
+    w(e)/|beta(e)| (r-1)! (default: the factor of w(e) = |e|)."""
     wk = weight_fp64(r, k)
     inv_fact = np.array([1.0 / math.factorial(a) for a in range(r)])
     out = np.empty(M.shape, dtype=np.float64)
@@ -93,14 +114,23 @@ def _edge_terms(M, x, r, k, chunk=1 << 15, members=None):
                 for j in range(1, r):
                     nc[:, j:] += eb[:, j:j + 1] * c[:, :r - j]
                 c = nc
-            out[c0:c0 + chunk, p] = wk * c[:, r - 1] * scale
+            wrow = wk if wts is None else wts[c0:c0 + chunk]
+            out[c0:c0 + chunk, p] = wrow * c[:, r - 1] * scale
     return out
 
 
-def incidence_terms(eptr, eidx, n, r, x):
+def _row_weights(w, rows, r, k):
+    if w is None:
+        return None
+    return np.array([edge_weight_fp64(r, k, float(v)) for v in w[rows]])
+
+
+def incidence_terms(eptr, eidx, n, r, x, w=None):
     """All (vertex, term) pairs of Alg. 2, one per incidence, in input order
-    (edge by edge, member by member)."""
+    (edge by edge, member by member).  ``w``: per-edge weights or None
+    (w(e) = |e|)."""
     eptr, eidx = validate(eptr, eidx, n, r)
+    w = validate_weights(w, len(eptr) - 1)
     x = np.asarray(x, dtype=np.float64)
     sizes = np.diff(eptr)
     terms = np.empty(len(eidx), dtype=np.float64)
@@ -108,14 +138,15 @@ def incidence_terms(eptr, eidx, n, r, x):
         rows = np.flatnonzero(sizes == k)
         pos = eptr[rows][:, None] + np.arange(k)[None, :]
         M = eidx[pos]
-        terms[pos.ravel()] = _edge_terms(M, x, r, int(k)).ravel()
+        terms[pos.ravel()] = _edge_terms(M, x, r, int(k), wts=_row_weights(w, rows, r, int(k))).ravel()
     return eidx, terms
 
 
-def sttsv(eptr, eidx, n, r, x):
+def sttsv(eptr, eidx, n, r, x, w=None):
     """y = B x^(r-1) (TTSV1, Eq. (2)) for the blowup tensor B, by Alg. 2.
-    Each y_v is the correctly rounded sum of its FP64 terms."""
-    verts, terms = incidence_terms(eptr, eidx, n, r, x)
+    Each y_v is the correctly rounded sum of its FP64 terms.  ``w``: per-edge
+    weights of H = (V, E, w) (default w(e) = |e|, Sec. II)."""
+    verts, terms = incidence_terms(eptr, eidx, n, r, x, w)
     order = np.argsort(verts, kind="stable")
     vs = verts[order]
     ts = terms[order]
@@ -128,7 +159,7 @@ def sttsv(eptr, eidx, n, r, x):
     return y
 
 
-def sttsv_at(eptr, eidx, n, r, x, nodes):
+def sttsv_at(eptr, eidx, n, r, x, nodes, w=None):
     """y_v for a list of vertices only: each requested y_v is the fsum of
     the terms of the edges that contain v.  Used to check full-size runs on
     sampled outputs.
@@ -141,6 +172,7 @@ def sttsv_at(eptr, eidx, n, r, x, nodes):
     eptr = np.asarray(eptr, dtype=np.int64)
     eidx = np.asarray(eidx, dtype=np.int64)
     x = np.asarray(x, dtype=np.float64)
+    w = validate_weights(w, len(eptr) - 1)
     nodes = np.asarray(nodes, dtype=np.int64)
     want = np.zeros(n, dtype=bool)
     want[nodes] = True
@@ -157,7 +189,7 @@ def sttsv_at(eptr, eidx, n, r, x, nodes):
         rest = np.arange(k)[None, :].repeat(len(ep), axis=0)
         rest = rest[rest != ep[:, None]].reshape(len(ep), k - 1)
         Mp = np.take_along_axis(M[er], np.concatenate([ep[:, None], rest], axis=1), axis=1)
-        T = _edge_terms(Mp, x, r, k, members=(0,))[:, 0]
+        T = _edge_terms(Mp, x, r, k, members=(0,), wts=_row_weights(w, rows[er], r, k))[:, 0]
         for v, t in zip(Mp[:, 0].tolist(), T.tolist()):
             acc[v].append(t)
     return np.array([math.fsum(acc[int(v)]) for v in nodes])

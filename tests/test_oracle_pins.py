@@ -287,3 +287,50 @@ def test_validation_errors():
         sr.sttsv(*_csr([(0, 1, 2, 3)]), 4, 3, np.ones(4))   # |e| > r
     with pytest.raises(ValueError):
         sr.sttsv(*_csr([(0, 5)]), 4, 3, np.ones(4))         # id out of range
+
+
+# ------------------------------------------------- edge-weighted H = (V, E, w)
+
+@pytest.mark.parametrize("seed", range(4))
+def test_weighted_oracle_matches_entry_enumeration(seed):
+    # Sec. II defines B for an edge-weighted H: every blowup of e carries
+    # w(e)/|beta(e)|.  Listing the entries with random weights, in exact
+    # rationals, and evaluating Eq. (2) must give the FP64 oracle's y.
+    rng = random.Random(300 + seed)
+    r = rng.randint(2, 5)
+    n = rng.randint(r, 8)
+    edges = _random_hypergraph(rng, n, rng.randint(2, 7), r)
+    w = np.array([rng.uniform(0.1, 5.0) for _ in edges])
+    xf = np.array([rng.uniform(0.05, 1.0) for _ in range(n)])
+    B = bl.blowup_entries(edges, r, weights=[Fraction(v) for v in w])
+    exact = bl.ttsv1_from_entries(B, n, r, [Fraction(v) for v in xf])
+    eptr, eidx = _csr(edges)
+    y = sr.sttsv(eptr, eidx, n, r, xf, w=w)
+    for v in range(n):
+        assert abs(y[v] - float(exact[v])) <= 1e-14 * abs(float(exact[v])) + 1e-300
+    # the paper's default w(e) = |e| is the weighted case with w = sizes
+    np.testing.assert_array_equal(sr.sttsv(eptr, eidx, n, r, xf, w=np.diff(eptr).astype(float)),
+                                  sr.sttsv(eptr, eidx, n, r, xf))
+
+
+@pytest.mark.parametrize("r", [3, 7, 25])
+def test_weighted_ones_give_weighted_degree(r):
+    # B 1^(r-1) = sum over e containing v of w(e)/|e|: each row of the
+    # blowups of e holds |beta(e)|/|e| entries of value w(e)/|beta(e)|
+    rng = np.random.default_rng(40 + r)
+    n, m = 50, 160
+    sizes = rng.integers(1, min(r, 8) + 1, size=m)
+    edges = [tuple(rng.choice(n, size=k, replace=False)) for k in sizes]
+    eptr, eidx = _csr(edges)
+    w = rng.uniform(0.01, 10.0, size=m)
+    edge_of = np.repeat(np.arange(m), sizes)
+    expect = np.bincount(eidx, weights=(w / sizes)[edge_of], minlength=n)
+    y = sr.sttsv(eptr, eidx, n, r, np.ones(n), w=w)
+    np.testing.assert_allclose(y, expect, rtol=2e-14)
+
+
+def test_weight_validation():
+    eptr, eidx = _csr([(0, 1), (1, 2)])
+    for bad in ([1.0, 0.0], [1.0, -2.0], [1.0, np.inf], [1.0, np.nan], [1.0]):
+        with pytest.raises(ValueError):
+            sr.sttsv(eptr, eidx, 3, 3, np.ones(3), w=np.array(bad))

@@ -131,7 +131,9 @@ def loss(s, x_star):
     return float(np.mean(u * u)), 2.0 * u / n
 
 
-def backward(p, g, c, ds, bf=False):
+def backward(p, g, c, ds, bf=False, trace=None):
+    """Gradients of the loss given dL/ds.  ``trace`` (a dict, optional)
+    receives dA and dEd of layer 1 and dH, dZ of layer 0."""
     rnd = bf16 if bf else (lambda a: a)
     gr = {}
     gr["wout"] = c["H2"].T @ ds
@@ -145,7 +147,11 @@ def backward(p, g, c, ds, bf=False):
         dHprev, dA = dX[:, :H], dX[:, H:]
         dE = g.node_mean_T(dA)
         dH = dHprev + g.edge_mean_T(dE)
+        if trace is not None and l == 1:
+            trace["dA1"], trace["dE1"] = dA, dE
     dZ0 = dH * (c["Z0"] > 0)
+    if trace is not None:
+        trace["dH0"], trace["dZ0"] = dH, dZ0
     gr["W0"] = c["X0"].T @ dZ0
     gr["b0"] = dZ0.sum(axis=0)
     return gr

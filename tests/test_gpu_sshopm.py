@@ -3,9 +3,12 @@
 
 Tolerances: contraction, lambda at every iterate, and every entry of the
 first iterate 1e-12 relative (FP64 series, all terms non-negative; entries
-below 1e-200 absolutely); later iterates 1e-12 absolute on the unit vector
-(the map raises small entries to the power r-1, so their relative rounding
-differences grow like (r-1)^K while the iterates localise); converged pairs:
+below 1e-200 absolutely).  Later iterates: every entry at or above 1e-6 of the
+largest 1e-12 relative, the rest 1e-12 on the unit vector's scale -- an entry
+fed by (r-1)-th powers of other small entries carries r-1 times their relative
+error, so rounding differences between two correct runs can grow like
+(r-1)^K there; the oracle tests pin the iteration against exact arithmetic
+and measure that drift (tests/test_sshopm_oracle_pins.py).  Converged pairs:
 lambda 1e-10, x 1e-6 absolute (the two runs may stop one update apart).
 """
 import sys
@@ -96,10 +99,8 @@ def test_sshopm_iterates_match_oracle(torch_cuda, name, seed, n, m, r, kmin, kma
             if K <= 1:
                 assert not bad.any()
             else:
-                # an entry fed mainly by (r-1)-th powers of other small entries
-                # carries r-1 times their relative error, so entrywise relative
-                # differences of rounding size grow like (r-1)^K on the small
-                # entries (the iterates localise); compare on the unit vector's scale
+                big = np.abs(xr) >= 1e-6 * np.max(np.abs(xr))
+                assert not bad[big].any(), np.flatnonzero(bad & big)[:5]
                 assert np.max(np.abs(xk - xr)) <= 1e-12
 
 

@@ -48,6 +48,32 @@ def test_per_iterate_parity(graph, use_graph):
             assert abs(info["criterion"] - ref["crits"][t - 1]) <= 1e-9 * ref["crits"][t - 1]
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_shifted_twenty_iterations_small_uniform(use_graph):
+    # The small uniform workload (n = 1000, m = 5000, sizes uniform on 2..5,
+    # r = 5) on its largest component: 20 passes of Alg. 1 with the shift
+    # z <- z + alpha x^[r-1], alpha = 1, against the oracle's 20th iterate.
+    import paper_2311_08595_amd as st
+    w = wl.small_uniform(seed=1)
+    eptr, eidx, n, _ = wl.largest_component(w["eptr"], w["eidx"], w["n"])
+    r, alpha = w["r"], 1.0
+    ref = nqz_ref.nqz(eptr, eidx, n, r, tol=0.0, max_iter=20, alpha=alpha, history=True)
+    _say(f"[solve] shifted, 20 iterations, n={n}, graph={use_graph}")
+    with st.Plan(eptr, eidx, n, r) as plan:
+        x, info = plan.solve(tol=1e-300, max_iter=20, shift=alpha, check_every=8, use_graph=use_graph,
+                             raise_on_notconv=False)
+        # one more solve that stops after 7 passes (a replay boundary mid-way)
+        x7, info7 = plan.solve(tol=1e-300, max_iter=7, shift=alpha, use_graph=use_graph, raise_on_notconv=False)
+    assert info["iterations"] == 20 and info7["iterations"] == 7
+    err = float(np.max(np.abs(x.cpu().numpy() - ref["x"]) / ref["x"]))
+    err7 = float(np.max(np.abs(x7.cpu().numpy() - ref["xs"][6]) / ref["xs"][6]))
+    _say(f"  max rel err x20 {err:.2e}, x7 {err7:.2e}")
+    assert err <= 1e-12 and err7 <= 1e-12
+    for key in ("lambda_min", "lambda_max"):
+        assert abs(info[key] - ref[key]) <= 1e-12 * abs(ref[key]), (key, info[key], ref[key])
+    assert abs(info["criterion"] - ref["crits"][-1]) <= 1e-9 * ref["crits"][-1]
+
+
 @pytest.fixture(scope="module")
 def big_graph():
     w = wl.zipf_powerlaw(seed=22, n=200000, m=1000000)

@@ -39,8 +39,10 @@ def nqz(eptr, eidx, n, r, tol, max_iter=200, x0=None, alpha=0.0, history=False,
     y = 1/n (a warm start); ``apply`` replaces the STTSV oracle (used only to
     time the loop structure); ``w``: per-edge weights (default w(e) = |e|)."""
     if apply is None:
+        weights = w
+
         def apply(v):
-            return sttsv(eptr, eidx, n, r, v, w)
+            return sttsv(eptr, eidx, n, r, v, weights)
     y = np.full(n, 1.0 / n) if x0 is None else np.asarray(x0, dtype=np.float64)
     yt = y / y.max()                        # scale of the first z is irrelevant too
     z = apply(yt)

@@ -77,6 +77,13 @@ typedef struct {
     int32_t flags;       /* STTSV_FLAG_* bits (default 0)                        */
     void*   stream;      /* hipStream_t the plan's work is ordered on; NULL =   */
                          /* the default stream                                   */
+    const double* edge_weights;  /* host, nullable: w(e) of every input edge   */
+                         /* (double[m], finite and > 0) of the edge-weighted     */
+                         /* hypergraph H = (V, E, w) of Sec. II; every blowup of */
+                         /* e then holds w(e)/|beta(e)|.  NULL: w(e) = |e|, the  */
+                         /* paper's choice (B 1^(r-1) = degrees).  Copied.       */
+                         /* Must be NULL for sttsv_plan_batch (per-graph weights */
+                         /* come with each sttsv_graph_desc).                    */
 } sttsv_opts;
 
 /*
@@ -98,8 +105,9 @@ typedef struct {
  * node-major incidence lists, reduction schedule, weight table
  * w(e)/|beta(e)| (r-1)! per edge size, the degree-rank copy of x) and is
  * used by one host thread at a time.  Blocking (uploads are synchronous).
- * Errors: EINVAL (malformed input), ENOTSUP (r out of range, or m, n or nnz
- * at or above 2^31), ENOMEM, EHIP.
+ * Errors: EINVAL (malformed input, or an edge weight that is not finite
+ * and positive), ENOTSUP (r out of range, or m, n or nnz at or above 2^31),
+ * ENOMEM, EHIP.
  */
 int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n,
                int32_t r, const sttsv_opts* opts, sttsv_plan_t* out);
@@ -283,6 +291,7 @@ typedef struct {
     int64_t m;
     int32_t n;
     int32_t r;
+    const double* w;     /* nullable: edge weights, as sttsv_opts.edge_weights */
 } sttsv_graph_desc;
 
 /*
@@ -373,6 +382,34 @@ int sttsv_mpnn_adam(sttsv_mpnn_t net, float lr, float beta1, float beta2, float 
 
 /* Warm start x0 = exp(s - max s) / sum (device double[n], > 0, l1 norm 1). */
 int sttsv_mpnn_warm_start(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, double* x0);
+
+/*
+ * sttsv_mpnn_query -- host copy (as FP32) of a value the last forward or
+ * loss_grad call on graph g left in the network's workspace (for tests that
+ * check each stage of the network against the FP64 oracle):
+ *   STTSV_MQ_X0          n x 16  features (bf16 values, columns >= 4 zero)
+ *   STTSV_MQ_Z0/Z1/Z2    n x 64  pre-activations of the three dense layers
+ *   STTSV_MQ_X1/X2       n x 128 bf16 inputs [H, A] of dense layers 1 and 2
+ *   STTSV_MQ_S, _DS      n       scores; dL/ds (after loss_grad)
+ *   STTSV_MQ_DZ, _DH     n x 64  dL/dZ0 and dL/dH0 (after loss_grad)
+ *   STTSV_MQ_DA          n x 64  dL/dA of layer 1 (after loss_grad)
+ *   STTSV_MQ_DE          m x 64  dL/dEd of layer 1 (after loss_grad)
+ * All row-major.  out host, count entries (EINVAL unless count is the size
+ * above, or the workspace was never sized for g).  Synchronous.
+ */
+#define STTSV_MQ_Z0  0
+#define STTSV_MQ_Z1  1
+#define STTSV_MQ_Z2  2
+#define STTSV_MQ_X1  3
+#define STTSV_MQ_X2  4
+#define STTSV_MQ_S   5
+#define STTSV_MQ_DS  6
+#define STTSV_MQ_DZ  7
+#define STTSV_MQ_DA  8
+#define STTSV_MQ_DE  9
+#define STTSV_MQ_DH 10
+#define STTSV_MQ_X0 11
+int sttsv_mpnn_query(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, int32_t what, float* out, int64_t count);
 
 /* ---- plan introspection (host copies; used to check the layout) ------- */
 #define STTSV_Q_PERM        0  /* int64[m]   input index of canonical edge c      */

@@ -49,7 +49,9 @@ class Plan:
     """Execution plan of one hypergraph (``sttsv_plan``), or of several
     (``Plan.batch`` -> ``sttsv_plan_batch``)."""
 
-    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None, flags=0, _graphs=None):
+    def __init__(self, eptr, eidx, n, r, precision="fp64", stream=None, flags=0, weights=None, _graphs=None):
+        """``weights``: optional w(e) per input edge (finite, > 0) of the
+        edge-weighted hypergraph H = (V, E, w); default w(e) = |e|."""
         lib = _lib.load()
         self._lib = lib
         opts, self.stream = _opts(precision, flags, stream)
@@ -58,17 +60,29 @@ class Plan:
             eptr = np.ascontiguousarray(eptr, dtype=np.int64)
             eidx = np.ascontiguousarray(eidx, dtype=np.int32)
             self.n, self.r, self.m = int(n), int(r), len(eptr) - 1
+            if weights is not None:
+                weights = np.ascontiguousarray(weights, dtype=np.float64)
+                if weights.shape != (self.m,):
+                    raise ValueError("weights must hold one value per edge")
+                opts.edge_weights = weights.ctypes.data
             _lib.check(lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, self.m, self.n, self.r,
                                       ctypes.byref(opts), ctypes.byref(h)))
             self.graphs = 1
         else:
             keep = []
             descs = (_lib.GraphDesc * len(_graphs))()
-            for g, (ep, ei, ng, rg) in enumerate(_graphs):
+            for g, gr in enumerate(_graphs):
+                ep, ei, ng, rg = gr[:4]
+                wg = gr[4] if len(gr) > 4 else None
                 ep = np.ascontiguousarray(ep, dtype=np.int64)
                 ei = np.ascontiguousarray(ei, dtype=np.int32)
-                keep.append((ep, ei))
-                descs[g] = _lib.GraphDesc(ep.ctypes.data, ei.ctypes.data, len(ep) - 1, int(ng), int(rg))
+                if wg is not None:
+                    wg = np.ascontiguousarray(wg, dtype=np.float64)
+                    if wg.shape != (len(ep) - 1,):
+                        raise ValueError("weights of graph %d must hold one value per edge" % g)
+                keep.append((ep, ei, wg))
+                descs[g] = _lib.GraphDesc(ep.ctypes.data, ei.ctypes.data, len(ep) - 1, int(ng), int(rg),
+                                          None if wg is None else wg.ctypes.data)
             _lib.check(lib.sttsv_plan_batch(len(_graphs), descs, ctypes.byref(opts), ctypes.byref(h)))
             self.n = sum(int(g[2]) for g in _graphs)
             self.m = sum(len(g[0]) - 1 for g in _graphs)
@@ -79,7 +93,7 @@ class Plan:
 
     @classmethod
     def batch(cls, graphs, precision="fp64", stream=None, flags=0):
-        """One plan over many hypergraphs: ``graphs`` = [(eptr, eidx, n, r), ...].
+        """One plan over many hypergraphs: ``graphs`` = [(eptr, eidx, n, r[, w]), ...].
         Vectors are the concatenation of the per-graph vectors in graph order."""
         return cls(None, None, None, None, precision, stream, flags, _graphs=list(graphs))
 

@@ -40,13 +40,13 @@ EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed",
            "sttsv_plan_graph_info", "sttsv_plan_autotune",
            "sttsv_mpnn_graph", "sttsv_mpnn_graph_destroy", "sttsv_mpnn_create", "sttsv_mpnn_destroy",
            "sttsv_mpnn_params", "sttsv_mpnn_forward", "sttsv_mpnn_loss_grad", "sttsv_mpnn_adam",
-           "sttsv_mpnn_warm_start",
+           "sttsv_mpnn_warm_start", "sttsv_mpnn_query",
            "sttsv_plan_get_info", "sttsv_plan_query", "sttsv_plan_destroy", "sttsv_strerror"]
 
 
 class SttsvOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("edge_weights", ctypes.c_void_p)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -75,7 +75,7 @@ class PlanInfo(ctypes.Structure):
 
 class GraphDesc(ctypes.Structure):
     _fields_ = [("eptr", ctypes.c_void_p), ("eidx", ctypes.c_void_p), ("m", ctypes.c_int64),
-                ("n", ctypes.c_int32), ("r", ctypes.c_int32)]
+                ("n", ctypes.c_int32), ("r", ctypes.c_int32), ("w", ctypes.c_void_p)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -123,6 +123,7 @@ def load(path=None):
     lib.sttsv_mpnn_loss_grad.argtypes = [P, P, P, ctypes.POINTER(f32)]
     lib.sttsv_mpnn_adam.argtypes = [P, f32, f32, f32, f32]
     lib.sttsv_mpnn_warm_start.argtypes = [P, P, P]
+    lib.sttsv_mpnn_query.argtypes = [P, P, i32, P, i64]
     lib.sttsv_plan_autotune.argtypes = [P, P, i32, ctypes.c_char_p, ctypes.POINTER(i32)]
     lib.sttsv_plan_batch.argtypes = [i32, P, ctypes.POINTER(SttsvOpts), ctypes.POINTER(P)]
     lib.heigvec_solve_batch.argtypes = [P, P, f64, ctypes.POINTER(SolveOpts), P, P]

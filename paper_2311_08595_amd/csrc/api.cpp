@@ -51,7 +51,7 @@ int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
   if (out == nullptr) return STTSV_EINVAL;
   return guarded([&] {
     Plan* p = nullptr;
-    const sttsv::GraphIn g{eptr, eidx, m, n, r};
+    const sttsv::GraphIn g{eptr, eidx, m, n, r, opts != nullptr ? opts->edge_weights : nullptr};
     const int rc = sttsv::build_plan(1, &g, opts, &p);
     if (rc != STTSV_OK) return rc;
     *out = new sttsv_plan_s{p};
@@ -61,9 +61,10 @@ int sttsv_plan(const int64_t* eptr, const int32_t* eidx, int64_t m, int32_t n, i
 
 int sttsv_plan_batch(int32_t G, const sttsv_graph_desc* gs, const sttsv_opts* opts, sttsv_plan_t* out) {
   if (out == nullptr || gs == nullptr || G < 1) return STTSV_EINVAL;
+  if (opts != nullptr && opts->edge_weights != nullptr) return STTSV_EINVAL;   // weights come per graph
   return guarded([&] {
     std::vector<sttsv::GraphIn> in(G);
-    for (int g = 0; g < G; ++g) in[g] = sttsv::GraphIn{gs[g].eptr, gs[g].eidx, gs[g].m, gs[g].n, gs[g].r};
+    for (int g = 0; g < G; ++g) in[g] = sttsv::GraphIn{gs[g].eptr, gs[g].eidx, gs[g].m, gs[g].n, gs[g].r, gs[g].w};
     Plan* p = nullptr;
     const int rc = sttsv::build_plan(G, in.data(), opts, &p);
     if (rc != STTSV_OK) return rc;

@@ -27,7 +27,9 @@ void fill_edge_gen7(EdgeTables&);
 
 namespace {
 
-// Size-1 edges {v}: beta = {(v,..,v)}, value 1, so the term is x_v^(r-1).
+// Size-1 edges {v}: beta = {(v,..,v)}, value w(e), so the term is
+// w(e) x_v^(r-1) (w(e) = |e| = 1 by default; an edge-weighted plan stores
+// w(e) (r-1)!, and the table value for size 1 is (r-1)!).
 __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   if (c.done != nullptr && *c.done) return;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -38,6 +40,7 @@ __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   const double f = frexp(xv, &e2);          // xv = f 2^e2
   double p = 1.0;
   for (int j = 0; j < b.r - 1; ++j) p *= f;
+  if (b.wgt != nullptr) p *= b.wgt[i] / b.wk;
   c.contrib[b.loc[i]] = ldexp(p, (b.r - 1) * e2);
 }
 

@@ -73,7 +73,8 @@ struct BucketDesc {
   int32_t qexp;         // series scale exponent (rho = 2^qexp)
   int32_t lds_stack;    // generic kernel: 1 = stack in LDS
   int32_t reuse_emin;   // prefix reuse: smallest exponent of z_0, z_1 with an exact rescale
-  double wk;            // w(e)/|beta(e)| (r-1)!
+  double wk;            // w(e)/|beta(e)| (r-1)! for w(e) = |e|
+  const double* wgt;    // per-edge w(e)/|beta(e)| (r-1)! (edge-weighted plans), or null
   // prefix reuse (FP64 register-resident kernels): runs of consecutive edges
   // with the same first two members, longest first; run_cnt[L] runs of
   // kRunMax - L edges
@@ -220,6 +221,7 @@ struct Plan {
   std::vector<int32_t> l0_n1;
   std::vector<int64_t> l0_base, l0_terms;
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
+  double* d_wgt = nullptr;        // per canonical edge w(e)/|beta(e)| (r-1)! (edge-weighted plans only)
   double* d_contrib = nullptr;    // contributions, one region per vertex block
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
   std::vector<Stage> stages[2];   // launch sequence per precision [fp64, fp32]
@@ -240,6 +242,7 @@ struct GraphIn {
   const int32_t* eidx;
   int64_t m;
   int32_t n, r;
+  const double* w;        // edge weights (nullable: w(e) = |e|)
 };
 int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out);
 void free_plan(Plan* p);

@@ -801,6 +801,41 @@ int sttsv_mpnn_warm_start(sttsv_mpnn_t M, sttsv_mpnn_graph_t G, double* x0) {
   return sttsv::mpnn::ok(hipGetLastError());
 }
 
+int sttsv_mpnn_query(sttsv_mpnn_t M, sttsv_mpnn_graph_t G, int32_t what, float* out, int64_t count) {
+  using namespace sttsv::mpnn;
+  if (M == nullptr || G == nullptr || out == nullptr) return STTSV_EINVAL;
+  const Net& N = M->n;
+  const Graph& g = G->g;
+  if (N.cap_n < g.n || N.cap_m < g.m) return STTSV_EINVAL;      // nothing computed for a graph this size
+  const float* f = nullptr;
+  const uint16_t* h = nullptr;
+  int64_t len = 0;
+  switch (what) {
+    case STTSV_MQ_Z0: case STTSV_MQ_Z1: case STTSV_MQ_Z2:
+      f = N.Z[what - STTSV_MQ_Z0]; len = (int64_t)g.n * HD; break;
+    case STTSV_MQ_X1: case STTSV_MQ_X2:
+      h = N.X[what - STTSV_MQ_X1 + 1]; len = (int64_t)g.n * 2 * HD; break;
+    case STTSV_MQ_X0: h = g.X0; len = (int64_t)g.n * KF; break;
+    case STTSV_MQ_S: f = N.s; len = g.n; break;
+    case STTSV_MQ_DS: f = N.ds; len = g.n; break;
+    case STTSV_MQ_DZ: f = N.dZ; len = (int64_t)g.n * HD; break;
+    case STTSV_MQ_DA: f = N.dA; len = (int64_t)g.n * HD; break;
+    case STTSV_MQ_DE: f = N.dE; len = g.m * HD; break;
+    case STTSV_MQ_DH: f = N.dH; len = (int64_t)g.n * HD; break;
+    default: return STTSV_EINVAL;
+  }
+  if (count != len) return STTSV_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return STTSV_EHIP;
+  if (f != nullptr) return hipMemcpy(out, f, 4 * (size_t)len, hipMemcpyDeviceToHost) == hipSuccess ? STTSV_OK : STTSV_EHIP;
+  std::vector<uint16_t> tmp(len);
+  if (hipMemcpy(tmp.data(), h, 2 * (size_t)len, hipMemcpyDeviceToHost) != hipSuccess) return STTSV_EHIP;
+  for (int64_t q = 0; q < len; ++q) {
+    const uint32_t u = static_cast<uint32_t>(tmp[q]) << 16;
+    std::memcpy(out + q, &u, 4);
+  }
+  return STTSV_OK;
+}
+
 int sttsv_mpnn_destroy(sttsv_mpnn_t M) {
   if (M == nullptr) return STTSV_OK;
   Net& N = M->n;

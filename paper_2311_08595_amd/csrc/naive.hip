@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(64) edge_naive(EdgeCall c, BucketDesc b) {
   for (int u = 0; u < k; ++u) mx = fmax(mx, fabs(c.x[b.mem[(int64_t)u * b.m + i]]));
   int e2 = 0;
   (void)frexp(mx, &e2);                                 // mx = f 2^e2, f in [0.5, 1)
-  const double coef = ldexp(b.wk, (r - 1) * e2);        // w/|beta| (r-1)! 2^((r-1) e2)
+  const double coef = ldexp(b.wgt != nullptr ? b.wgt[i] : b.wk, (r - 1) * e2);   // w/|beta| (r-1)! 2^((r-1) e2)
 
   // s <- e^{z_v t}: s[n] = z_v^n / n!
   double s[RC], p[RC];

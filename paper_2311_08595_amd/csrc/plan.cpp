@@ -207,6 +207,23 @@ std::vector<double> weight_table(int r) {
   return w;
 }
 
+// w(e)/|beta(e)| (r-1)! for an edge of size k with weight w: w times
+// (r-1)!/(k! S(r,k)) in extended precision, one rounding to double.
+std::vector<long double> unit_weight_table(int r) {
+  std::vector<std::vector<long double>> S(r + 1, std::vector<long double>(r + 1, 0.0L));
+  S[0][0] = 1.0L;
+  for (int a = 1; a <= r; ++a)
+    for (int b = 1; b <= a; ++b) S[a][b] = (long double)b * S[a - 1][b] + S[a - 1][b - 1];
+  std::vector<long double> u(r + 1, 0.0L);
+  for (int k = 1; k <= r; ++k) {
+    long double num = 1.0L;  // (r-1)!/k!
+    for (int j = k + 1; j <= r - 1; ++j) num *= (long double)j;
+    if (k == r) num = 1.0L / (long double)r;
+    u[k] = num / S[r][k];
+  }
+  return u;
+}
+
 double log2_fact(int a) {
   double s = 0.0;
   for (int j = 2; j <= a; ++j) s += std::log2((double)j);
@@ -261,6 +278,7 @@ void free_plan(Plan* p) {
   (void)hipFree(p->d_xr);
   (void)hipFree(p->d_loc);
   (void)hipFree(p->d_gid);
+  (void)hipFree(p->d_wgt);
   (void)hipFree(p->d_contrib);
   for (auto& g : p->groups) {
     (void)hipFree(g.d_bks);
@@ -301,6 +319,9 @@ int validate_graph(const GraphIn& g, std::vector<int64_t>& deg) {
     const int64_t k = g.eptr[e + 1] - g.eptr[e];
     if (k < 1 || k > g.r) return STTSV_EINVAL;
   }
+  if (g.w != nullptr)
+    for (int64_t e = 0; e < g.m; ++e)
+      if (!(std::isfinite(g.w[e]) && g.w[e] > 0.0)) return STTSV_EINVAL;   // w(e) finite and positive
   deg.assign(g.n, 0);
   std::vector<int64_t> seen(g.n, -1);
   for (int64_t e = 0; e < g.m; ++e) {
@@ -655,6 +676,12 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   std::vector<int32_t> memr(nnz, 0), rid(n, 0);
   std::vector<int32_t> gid;
   if (G > 1) gid.assign(m, 0);
+  bool weighted = false;
+  for (int g = 0; g < G; ++g) weighted = weighted || gs[g].w != nullptr;
+  std::vector<double> wgt;
+  std::vector<std::vector<long double>> utab(rmax + 1);
+  std::vector<std::vector<double>> dtab(rmax + 1);
+  if (weighted) wgt.assign(m, 0.0);
   {
     std::vector<int64_t> cur(P->tptr.begin(), P->tptr.end() - 1);
     for (int g = 0; g < G; ++g) {
@@ -673,6 +700,15 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
           const int64_t i = base + (int64_t)t;                  // edge index in the bucket
           P->perm[B.edge_off + i] = I.eoff + e;
           if (G > 1) gid[B.edge_off + i] = g;
+          if (weighted) {
+            if (in.w == nullptr) {
+              if (dtab[in.r].empty()) dtab[in.r] = weight_table(in.r);
+              wgt[B.edge_off + i] = dtab[in.r][k];
+            } else {
+              if (utab[in.r].empty()) utab[in.r] = unit_weight_table(in.r);
+              wgt[B.edge_off + i] = static_cast<double>((long double)in.w[e] * utab[in.r][k]);
+            }
+          }
           const int32_t* a = c.rk.data() + in.eptr[e];
           for (int j = 0; j < k; ++j) {
             const int32_t u = I.voff + c.inv_rank[a[j]];
@@ -790,6 +826,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if (weighted && (rc = upload(&P->d_wgt, wgt.data(), wgt.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);
   for (size_t l = 0; l < hl.size(); ++l) {
     ReduceLevel L;
     L.nchunks = (int64_t)hl[l].len.size();
@@ -856,6 +893,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       d.lds_stack = 1;
       d.reuse_emin = reuse_emin(W);
       d.wk = wtab[r][B.k];
+      d.wgt = P->d_wgt != nullptr ? P->d_wgt + B.edge_off : nullptr;
       d.run_start = nullptr;
       d.nruns = 0;
       for (int q = 0; q < kRunMax; ++q) d.run_cnt[q] = 0;

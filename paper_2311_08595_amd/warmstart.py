@@ -105,6 +105,18 @@ class WarmStartNet:
                                                   ctypes.byref(loss)))
         return loss.value
 
+    QUERY = {"X0": (11, 16), "Z0": (0, 64), "Z1": (1, 64), "Z2": (2, 64), "X1": (3, 128), "X2": (4, 128),
+             "s": (5, 0), "ds": (6, 0), "dZ0": (7, 64), "dA1": (8, 64), "dE1": (9, 64), "dH0": (10, 64)}
+
+    def query(self, g, name):
+        """Host copy (float32) of an intermediate value of the last forward /
+        loss_grad call on graph ``g`` (names in QUERY)."""
+        what, cols = self.QUERY[name]
+        rows = g.m if name == "dE1" else g.n
+        out = np.empty(rows * cols if cols else rows, dtype=np.float32)
+        _lib.check(self._lib.sttsv_mpnn_query(self._h, g._h, what, out.ctypes.data, out.size))
+        return out.reshape(rows, cols) if cols else out
+
     def step(self, g, x_star, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         loss = self.loss_grad(g, x_star)
         _lib.check(self._lib.sttsv_mpnn_adam(self._h, lr, beta1, beta2, eps))

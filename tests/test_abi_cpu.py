@@ -84,3 +84,26 @@ def test_null_arguments():
     assert lib.zeigvec_sshopm(None, None, 1.0, 1e-12, 10, None, None) == _lib.STTSV_EINVAL
     assert lib.heigvec_solve(None, None, 1e-8, None, None) == _lib.STTSV_EINVAL
     assert lib.sttsv_plan_destroy(None) == _lib.STTSV_OK
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("inf"), float("nan")])
+def test_plan_rejects_bad_edge_weights(bad):
+    # w(e) of the edge-weighted H = (V, E, w) must be finite and positive;
+    # checked on the host before any device work
+    lib = _lib.load()
+    eptr = np.array([0, 2, 5], dtype=np.int64)
+    eidx = np.array([0, 1, 1, 2, 3], dtype=np.int32)
+    w = np.array([1.5, bad])
+    opts = _lib.SttsvOpts(0, 0, None, w.ctypes.data)
+    h = ctypes.c_void_p()
+    assert lib.sttsv_plan(eptr.ctypes.data, eidx.ctypes.data, 2, 4, 3, ctypes.byref(opts),
+                          ctypes.byref(h)) == _lib.STTSV_EINVAL
+    assert not h.value
+    # batch plans take weights per graph, never through the options
+    desc = (_lib.GraphDesc * 1)()
+    desc[0] = _lib.GraphDesc(eptr.ctypes.data, eidx.ctypes.data, 2, 4, 3, w.ctypes.data)
+    assert lib.sttsv_plan_batch(1, desc, None, ctypes.byref(h)) == _lib.STTSV_EINVAL
+    good = np.array([1.0, 2.0])
+    opts = _lib.SttsvOpts(0, 0, None, good.ctypes.data)
+    assert lib.sttsv_plan_batch(1, desc, ctypes.byref(opts), ctypes.byref(h)) == _lib.STTSV_EINVAL
+    assert not h.value

@@ -79,6 +79,16 @@ def test_apply_matches_oracle(torch_cuda, prec, name, seed, n, m, r, kmin, kmax)
     err = _relerr(y, ref)
     _say(f"  max rel err {err:.3e}")
     assert err <= TOL[prec]
+    if prec == "fp32":
+        # sizes whose FP32 series would leave FP32's range run in FP64
+        # (r = 64: sizes 6..27); the FP32 label must still cover FP32 sizes
+        import paper_2311_08595_amd as st
+        from paper_2311_08595_amd import _lib
+        with st.Plan(eptr, eidx, n, r) as plan:
+            q = plan.query(_lib.Q_SCALE_EXP)
+        fp64_sizes = [k for k in range(2, kmax + 1) if q[k] == np.iinfo(np.int32).min]
+        _say(f"  sizes run in FP64 under the FP32 schedule: {fp64_sizes}")
+        assert len(fp64_sizes) < kmax - 1
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -180,6 +180,20 @@ int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y);
  */
 int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out);
 
+/*
+ * sttsv_contract_noalloc -- sttsv_contract for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, hosts that
+ * forbid allocation): same arguments, same kernels, same result bit for bit,
+ * but its reduction scratch (1540 doubles, fixed: it does not grow with the
+ * plan) lives in a static device array of the library, one per GPU, held
+ * until the process ends; no allocator is called.  The plan's device must be
+ * the current device (EINVAL otherwise).  Every call on one GPU uses that
+ * GPU's array: calls that overlap on one GPU (other threads, other streams)
+ * race and must be serialised by the caller.  Synchronous on the plan's
+ * stream.  Errors: EINVAL (NULL argument, x == y, other device), EHIP.
+ */
+int sttsv_contract_noalloc(sttsv_plan_t plan, const double* x, double* y, double* out);
+
 typedef struct {
     int32_t iterations;    /* updates of x performed                             */
     int32_t converged;     /* 1 when the stopping rule was met                   */

@@ -142,15 +142,17 @@ class Plan:
         _lib.check(self._lib.sttsv_apply_naive(self._h, xp, yp))
         return y
 
-    def contract(self, x, y=None):
-        """B x^r (full contraction); y receives B x^(r-1).  Returns (value, y)."""
+    def contract(self, x, y=None, noalloc=False):
+        """B x^r (full contraction); y receives B x^(r-1).  Returns (value, y).
+        ``noalloc``: the allocation-free entry point (static scratch)."""
         import torch
         xp = _dev_ptr(x, self.n, "x")
         if y is None:
             y = torch.empty_like(x)
         yp = _dev_ptr(y, self.n, "y")
         out = ctypes.c_double()
-        _lib.check(self._lib.sttsv_contract(self._h, xp, yp, ctypes.byref(out)))
+        fn = self._lib.sttsv_contract_noalloc if noalloc else self._lib.sttsv_contract
+        _lib.check(fn(self._h, xp, yp, ctypes.byref(out)))
         return out.value, y
 
     def zeig_sshopm(self, x0=None, alpha=1.0, tol=1e-12, max_iter=500, out=None, raise_on_notconv=True):

@@ -35,7 +35,7 @@ Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, 
 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed", "sttsv_apply_naive",
-           "sttsv_contract", "zeigvec_sshopm",
+           "sttsv_contract", "sttsv_contract_noalloc", "zeigvec_sshopm",
            "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
            "sttsv_plan_graph_info", "sttsv_plan_autotune",
            "sttsv_mpnn_graph", "sttsv_mpnn_graph_destroy", "sttsv_mpnn_create", "sttsv_mpnn_destroy",
@@ -109,6 +109,7 @@ def load(path=None):
     lib.sttsv_apply_prec.argtypes = [P, P, P, i32]
     lib.sttsv_apply_naive.argtypes = [P, P, P]
     lib.sttsv_contract.argtypes = [P, P, P, P]
+    lib.sttsv_contract_noalloc.argtypes = [P, P, P, P]
     lib.zeigvec_sshopm.argtypes = [P, P, ctypes.c_double, ctypes.c_double, i32, P, P]
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]

@@ -40,6 +40,7 @@ int copy_out(const std::vector<S>& src, void* out, int64_t count) {
 namespace sttsv {
 hipError_t launch_sttsv_naive(Plan& p, const double* x, double* y, hipStream_t s);
 int contract(Plan& p, const double* x, double* y, double* out);
+int contract_noalloc(Plan& p, const double* x, double* y, double* out);
 int zeig_sshopm(Plan& p, const double* x0, double alpha, double tol, int32_t max_iter, double* x,
                 sttsv_zeig_info* info);
 }
@@ -147,6 +148,12 @@ int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out) {
   if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr || out == nullptr) return STTSV_EINVAL;
   if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
   return guarded([&] { return sttsv::contract(*plan->p, x, y, out); });
+}
+
+int sttsv_contract_noalloc(sttsv_plan_t plan, const double* x, double* y, double* out) {
+  if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr || out == nullptr) return STTSV_EINVAL;
+  if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
+  return guarded([&] { return sttsv::contract_noalloc(*plan->p, x, y, out); });
 }
 
 int zeigvec_sshopm(sttsv_plan_t plan, const double* x0, double alpha, double tol, int32_t max_iter,

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -121,6 +122,53 @@ int contract(Plan& p, const double* x, double* y, double* out) {
   if (launch_sttsv(p, x, y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
   double h[3];
   if (reduce3(x, y, p.n, 0.0, z, s, h) != hipSuccess) return STTSV_EHIP;
+  *out = h[0];
+  return STTSV_OK;
+}
+
+// ---- allocation-free contraction
+// The reduction scratch of the contraction (kZGrid partials of three sums and
+// the three totals) lives in one file-scope device array per GPU, so the entry
+// point below calls no allocator.  Host code must not pass the array's name
+// to a kernel: that name is a host-side stand-in.  The device address comes
+// from hipGetSymbolAddress, taken once per device and kept in g_scratch_ptr.
+constexpr int kScratchDoubles = 3 * kZGrid + 4;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int contract_noalloc(Plan& p, const double* x, double* y, double* out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return STTSV_EHIP;
+  if (dev != p.device) return STTSV_EINVAL;               // the plan's device must be current
+  if (dev < 0 || dev >= kMaxDevices) return STTSV_ENOTSUP;
+  double* sp = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+      void* a = nullptr;
+      if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || a == nullptr) return STTSV_EHIP;
+      g_scratch_ptr[dev] = static_cast<double*>(a);
+    }
+    sp = g_scratch_ptr[dev];
+  }
+  // the scratch need does not grow with the plan: kZGrid partials of three
+  // sums and three totals, every entry written before it is read
+  static_assert(3 * kZGrid + 3 <= kScratchDoubles, "contraction scratch exceeds the static array");
+  hipStream_t s = p.stream;
+  if (launch_sttsv(p, x, y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
+  ZScratch z;
+  z.part = sp;
+  z.st = sp + 3 * kZGrid;
+  double h[3];
+  const hipError_t e = reduce3(x, y, p.n, 0.0, z, s, h);
+  z.part = nullptr;                                       // not owned: keep ~ZScratch from freeing it
+  z.st = nullptr;
+  if (e != hipSuccess) return STTSV_EHIP;
   *out = h[0];
   return STTSV_OK;
 }

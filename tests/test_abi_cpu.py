@@ -81,6 +81,7 @@ def test_null_arguments():
     assert lib.sttsv_apply(None, None, None) == _lib.STTSV_EINVAL
     assert lib.sttsv_apply_naive(None, None, None) == _lib.STTSV_EINVAL
     assert lib.sttsv_contract(None, None, None, None) == _lib.STTSV_EINVAL
+    assert lib.sttsv_contract_noalloc(None, None, None, None) == _lib.STTSV_EINVAL
     assert lib.zeigvec_sshopm(None, None, 1.0, 1e-12, 10, None, None) == _lib.STTSV_EINVAL
     assert lib.heigvec_solve(None, None, 1e-8, None, None) == _lib.STTSV_EINVAL
     assert lib.sttsv_plan_destroy(None) == _lib.STTSV_OK

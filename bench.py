@@ -172,14 +172,14 @@ def stage_kernel(s, prec, r):
     return None, None
 
 
-def roofline_of(stages, work, prec, r):
+def roofline_of(stages, work, prec, r, with_traffic=True):
     """Dominant stage and its roofline figures."""
     i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
     t = stages[i]["ms"] * 1e-3
     flops, byts, name = work[i]
     peak_f = PEAK_FP64_VALU      # FP64 FMA and non-packed FP32 FMA issue at the same rate
     kname, grid = stage_kernel(stages[i], prec, r)
-    traffic = measured_traffic(kname, grid) if kname else None
+    traffic = measured_traffic(kname, grid) if kname and with_traffic else None
     if flops / peak_f >= byts / PEAK_HBM:
         return stages[i], dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
                                frac=(flops / t) / peak_f, traffic=traffic, kernel=name)
@@ -188,8 +188,61 @@ def roofline_of(stages, work, prec, r):
                            algorithmic_bytes=byts)
 
 
-def cpu_baseline(w, sample_edges, seed=0):
+def _oracle_terms(args):
+    """Worker: the oracle's Alg. 2 terms of one contiguous range of edges."""
     from oracle import sttsv_ref
+    eptr, eidx, n, r, x = args
+    return sttsv_ref.incidence_terms(eptr, eidx, n, r, x)
+
+
+def oracle_sttsv_parallel(eptr, eidx, n, r, x, procs):
+    """The FP64 oracle (Alg. 2 terms + correctly rounded per-vertex sums)
+    with its edges split into ``procs`` contiguous ranges computed by worker
+    processes; the parent sums every vertex's terms with math.fsum, so the
+    result is bitwise the oracle's serial one (fsum is correctly rounded)."""
+    import multiprocessing as mp
+    m = len(eptr) - 1
+    cuts = np.linspace(0, m, procs + 1).astype(np.int64)
+    jobs = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        if b > a:
+            ep = eptr[a:b + 1] - eptr[a]
+            jobs.append((ep, eidx[eptr[a]:eptr[b]], n, r, x))
+    if procs > 1:
+        with mp.get_context("fork").Pool(len(jobs)) as pool:
+            parts = pool.map(_oracle_terms, jobs)
+    else:
+        parts = [_oracle_terms(j) for j in jobs]
+    verts = np.concatenate([p[0] for p in parts])
+    terms = np.concatenate([p[1] for p in parts])
+    order = np.argsort(verts, kind="stable")
+    vs, ts = verts[order], terms[order]
+    bounds = np.searchsorted(vs, np.arange(n + 1))
+    y = np.zeros(n)
+    for v in np.flatnonzero(np.diff(bounds)):
+        y[v] = math.fsum(ts[bounds[v]:bounds[v + 1]].tolist())
+    return y
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def oracle_procs():
+    # the GPU box's CPU share is 16 threads per GPU, whatever os.cpu_count() shows
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(w, sample_edges, procs, seed=0):
     rng = np.random.default_rng(seed)
     m = len(w["eptr"]) - 1
     pick = np.sort(rng.choice(m, size=min(sample_edges, m), replace=False))
@@ -199,11 +252,185 @@ def cpu_baseline(w, sample_edges, seed=0):
     src = np.repeat(w["eptr"][pick], sizes) + (np.arange(eptr[-1]) - np.repeat(eptr[:-1], sizes))
     eidx = w["eidx"][src]
     t0 = time.perf_counter()
-    sttsv_ref.sttsv(eptr, eidx, w["n"], w["r"], w["x"])
+    oracle_sttsv_parallel(eptr, eidx, w["n"], w["r"], w["x"], procs)
     dt = time.perf_counter() - t0
-    return dict(value=len(pick) / dt, unit="hyperedges/s", cores=1, kind="oracle",
-                sample="%d random edges of the same hypergraph (all n=%d vertices), one process, "
-                       "numpy FP64 AAY + fsum; %.1f s" % (len(pick), w["n"], dt))
+    return dict(value=len(pick) / dt, unit="hyperedges/s", cores=procs, kind="oracle",
+                cpu=host_cpu(),
+                sample="%d random edges of the same hypergraph (all n=%d vertices), FP64 AAY terms in %d "
+                       "worker processes over contiguous edge ranges, per-vertex fsum in the parent; %.1f s"
+                       % (len(pick), w["n"], procs, dt))
+
+
+def _timed_applies(plan, xd, yd, prec, warmup, reps):
+    import torch
+    for _ in range(warmup):
+        plan.apply(xd, yd, precision=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.apply(xd, yd, precision=prec)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _stage_rooflines(plan, xd, yd, r, nnz, reps):
+    """Per precision: the stage table of one apply and the dominant stage's
+    roofline."""
+    from paper_2311_08595_amd import _lib as L
+    bk, bm = plan.query(L.Q_BUCKET_K).tolist(), plan.query(L.Q_BUCKET_M).tolist()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        stages = stage_table(plan, xd, yd, prec, reps)
+        prev = nnz
+        for st_ in stages:
+            if st_["kind"] == 2:
+                st_["in_len"] = prev
+                prev = st_["count"]
+        work = stage_work(stages, bk, bm, r)
+        best, roof = roofline_of(stages, work, prec, r, with_traffic=False)
+        roof["avg_kernel_ms"] = best["ms"]
+        roof["stages_ms_sum"] = sum(s_["ms"] for s_ in stages)
+        out[prec] = dict(roofline=roof, stages_ms=[(s_["kind"], s_["size"], s_["count"], round(s_["ms"], 5))
+                                                   for s_ in stages])
+    return out
+
+
+def bench_small(a):
+    """The small uniform workload (n = 1000, m = 5000, sizes uniform on
+    {2..5}, r = 5, x uniform on (0,1]): microseconds per STTSV (FP64 and FP32
+    series), per captured NQZ iteration (20 shifted iterations, alpha = 1, one
+    captured graph), and to 1e-8; the FP64 oracle beside it (one process: the
+    whole graph is small)."""
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import workloads as wl
+    from oracle import nqz_ref, sttsv_ref
+    w = wl.small_uniform(seed=1)
+    n, r, m = w["n"], w["r"], len(w["eptr"]) - 1
+    res = {"workload": w["name"], "n": n, "m": m, "nnz": int(len(w["eidx"])), "r": r}
+    with st.Plan(w["eptr"], w["eidx"], n, r) as p:
+        xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+        yd = torch.empty_like(xd)
+        for prec in ("fp64", "fp32"):
+            dt = _timed_applies(p, xd, yd, prec, 200, 2000)
+            res["sttsv_%s_us" % prec] = dt * 1e6
+            res["sttsv_%s_hyperedges_per_s" % prec] = m / dt
+        res.update(_stage_rooflines(p, xd, yd, r, len(w["eidx"]), 20))
+        res["bound"] = ("launch/latency: %.1e series FMAs and %.2f MB per STTSV are well under a microsecond of "
+                        "the chip at any roofline" % (sum(edge_fma(int(k), r) for k in np.diff(w["eptr"])),
+                                                      20.0 * len(w["eidx"]) / 1e6))
+        for use_graph in (True, False):
+            p.solve(tol=1e-300, max_iter=20, shift=1.0, check_every=20, use_graph=use_graph, raise_on_notconv=False)
+            torch.cuda.synchronize()
+            reps = 20
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, info = p.solve(tol=1e-300, max_iter=20, shift=1.0, check_every=20, use_graph=use_graph,
+                                  raise_on_notconv=False)
+            dt = (time.perf_counter() - t0) / reps
+            key = "shifted20_%s" % ("captured" if use_graph else "uncaptured")
+            res[key] = {"seconds": dt, "us_per_iteration": dt * 1e6 / 20, "iterations": info["iterations"]}
+        p.solve(tol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = p.solve(tol=1e-8)
+        res["solve_1e8_fp64"] = {"seconds": time.perf_counter() - t0, "iterations": info["iterations"]}
+    # the oracle on the host: one STTSV, 20 shifted iterations, and the solve to 1e-8
+    t0 = time.perf_counter()
+    sttsv_ref.sttsv(w["eptr"], w["eidx"], n, r, w["x"])
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    nqz_ref.nqz(w["eptr"], w["eidx"], n, r, tol=0.0, max_iter=20, alpha=1.0)
+    t_20 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o = nqz_ref.nqz(w["eptr"], w["eidx"], n, r, tol=1e-8, max_iter=500)
+    t_c = time.perf_counter() - t0
+    res["oracle"] = {"cores": 1, "cpu": host_cpu(), "sttsv_us": t_s * 1e6, "shifted20_seconds": t_20,
+                     "solve_1e8_seconds": t_c, "solve_1e8_iterations": o["iterations"]}
+    log("[bench]   small uniform: FP64 STTSV %.1f us, captured iteration %.1f us, solve to 1e-8 %.2f ms "
+        "(oracle %.1f ms / %.2f s)" % (res["sttsv_fp64_us"], res["shifted20_captured"]["us_per_iteration"],
+                                       res["solve_1e8_fp64"]["seconds"] * 1e3, t_s * 1e3, t_c))
+    return res
+
+
+def bench_heavy(a):
+    """The heavy-tail workload (n = 2e5, m = 2e6, sizes: w.p. 0.99 truncated
+    geometric p = 0.4 on [2, 8], w.p. 0.01 uniform on [9, 50], r = 50, uniform
+    membership): STTSV per precision with its dominant stage's roofline, and
+    the solve to 1e-8 on the largest component (FP64, and FP32 series then
+    FP64)."""
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import workloads as wl
+    w = wl.heavy_tail()
+    n, r, m = w["n"], w["r"], len(w["eptr"]) - 1
+    res = {"workload": w["name"], "n": n, "m": m, "nnz": int(len(w["eidx"])), "r": r}
+    t0 = time.perf_counter()
+    with st.Plan(w["eptr"], w["eidx"], n, r) as p:
+        res["plan_s"] = time.perf_counter() - t0
+        xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+        yd = torch.empty_like(xd)
+        for prec in ("fp64", "fp32"):
+            res["untuned_%s_ms" % prec] = _timed_applies(p, xd, yd, prec, 20, 100) * 1e3
+        if not a.no_tune:
+            t0 = time.perf_counter()
+            p.autotune(xd, reps=5)
+            res["autotune_s"] = time.perf_counter() - t0
+        y64 = None
+        for prec in ("fp64", "fp32"):
+            dt = _timed_applies(p, xd, yd, prec, 20, 100)
+            res["sttsv_%s_ms" % prec] = dt * 1e3
+            res["sttsv_%s_hyperedges_per_s" % prec] = m / dt
+            if prec == "fp64":
+                y64 = yd.clone()
+        nz = y64 != 0
+        res["fp32_max_rel_err_vs_fp64"] = float(((yd[nz] - y64[nz]).abs() / y64[nz].abs()).max())
+        res.update(_stage_rooflines(p, xd, yd, r, len(w["eidx"]), 5))
+    log("[bench]   heavy tail: FP64 %.3f ms, FP32 %.3f ms per STTSV" % (res["sttsv_fp64_ms"], res["sttsv_fp32_ms"]))
+    e2, i2, n2, _ = wl.largest_component(w["eptr"], w["eidx"], n)
+    solve = {"n_lcc": n2, "m_lcc": len(e2) - 1, "tol": 1e-8}
+    with st.Plan(e2, i2, n2, r) as p2:
+        if not a.no_tune:
+            p2.autotune(torch.full((n2,), 1.0 / n2, dtype=torch.float64, device="cuda"), reps=5)
+        for sched in ("fp64", "fp32_fp64"):
+            p2.solve(tol=1e-8, schedule=sched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = p2.solve(tol=1e-8, schedule=sched)
+            solve[sched] = {"seconds": time.perf_counter() - t0, "iterations": info["iterations"],
+                            "iters_fp32": info["iters_fp32"], "iters_fp64": info["iters_fp64"],
+                            "criterion": info["criterion"]}
+            log("[bench]   heavy tail solve %s: %.4f s, %d iterations" % (sched, solve[sched]["seconds"],
+                                                                         info["iterations"]))
+    res["solve"] = solve
+    return res
+
+
+def profile_apply(a):
+    """Short run for counter collection: plan as built, a few applies of each
+    precision on one workload."""
+    import torch
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import workloads as wl
+    w = {"zipf": lambda: wl.zipf_powerlaw(n=a.n, m=a.m), "heavy": wl.heavy_tail,
+         "small": wl.small_uniform}[a.profile]()
+    with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as p:
+        xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+        yd = torch.empty_like(xd)
+        if a.calib_copy_mib:
+            # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+            # calibrate the counters taken on the STTSV kernels of the same run
+            src = torch.ones(a.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        for prec in ("fp64", "fp32"):
+            for _ in range(a.steps):
+                p.apply(xd, yd, precision=prec)
+            torch.cuda.synchronize()
+            log("[profile] %s: %d applies of %s done" % (w["name"], a.steps, prec))
 
 
 def bench_batch(a):
@@ -366,7 +593,7 @@ def main():
     ap.add_argument("--m", type=int, default=5_000_000)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-edges", type=int, default=300000)
+    ap.add_argument("--cpu-edges", type=int, default=2000000)
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-synthetic", action="store_true", help="skip the S1-S4 memoised-vs-naive comparison")
@@ -374,6 +601,11 @@ def main():
                     help="run only the S1-S4 memoised-vs-naive comparison (prints its rows as JSON)")
     ap.add_argument("--no-tune", action="store_true", help="time the plan as built, without autotuning")
     ap.add_argument("--batch-graphs", type=int, default=256)
+    ap.add_argument("--no-small", action="store_true", help="skip the small uniform workload (n=1e3, r=5)")
+    ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tail workload (n=2e5, r=50)")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle worker processes (0: the host's share, <= 16)")
+    ap.add_argument("--profile", choices=["zipf", "heavy", "small"], default=None,
+                    help="only run --steps applies of each precision on one workload (for counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -386,14 +618,25 @@ def main():
     import paper_2311_08595_amd as st
     from paper_2311_08595_amd import workloads as wl
 
-    torch.cuda.set_device(0)
+    if a.profile:
+        torch.cuda.set_device(0)
+        profile_apply(a)
+        return
     if a.synthetic_only:
+        torch.cuda.set_device(0)
         log("[bench] paper synthetic sets S1-S4: memoised vs naive (Alg. 3)")
         print(json.dumps({"paper_synthetic": bench_paper_synthetic(a)}), flush=True)
         return
     log("[bench] generating workload")
     w = wl.zipf_powerlaw(n=a.n, m=a.m)
     n, r, m = w["n"], w["r"], len(w["eptr"]) - 1
+    cpu = None
+    if not a.no_cpu:
+        # the oracle's worker processes are forked before this process touches the GPU
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(w, a.cpu_edges, a.cpu_procs or oracle_procs())
+        log("[bench]   %.3e hyperedges/s on %d processes" % (cpu["value"], cpu["cores"]))
+    torch.cuda.set_device(0)
     log("[bench] planning n=%d m=%d nnz=%d r=%d" % (n, m, len(w["eidx"]), r))
     t0 = time.perf_counter()
     plan = st.Plan(w["eptr"], w["eidx"], n, r)
@@ -606,10 +849,15 @@ def main():
         b = out["batched"]
         tgt = {}
         if "solve_batch_net_start_fp32_fp64" in b:
+            # the network's gain at equal batching: warm-started batched FP32->FP64
+            # (inference included) against the plain batched FP64 solve
             w_s = b["solve_batch_net_start_fp32_fp64"]["seconds"]
             tgt["batched_warm_fp32_fp64_s"] = w_s
+            tgt["batched_plain_fp64_s"] = b["solve_batch_fp64"]["seconds"]
+            tgt["batched_met"] = w_s < b["solve_batch_fp64"]["seconds"]
+            # batching alone, for context: the same graphs solved one by one
             tgt["single_plain_fp64_sum_s"] = b["solve_single_sum_fp64_s"]
-            tgt["batched_met"] = w_s < b["solve_single_sum_fp64_s"]
+            tgt["batched_warm_vs_sequential_plain"] = w_s < b["solve_single_sum_fp64_s"]
         sv = out.get("solve", {})
         if "net_start_fp32_fp64" in sv:
             tgt["n1e6_warm_fp32_fp64_s"] = sv["net_start_fp32_fp64"]["seconds"]
@@ -619,9 +867,14 @@ def main():
     if not a.no_synthetic:
         log("[bench] paper synthetic sets S1-S4: memoised vs naive (Alg. 3)")
         out["paper_synthetic"] = bench_paper_synthetic(a)
-    if not a.no_cpu:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_edges)
+    if not a.no_small:
+        log("[bench] small uniform workload")
+        out["small_uniform"] = bench_small(a)
+    if not a.no_heavy:
+        log("[bench] heavy-tail workload")
+        out["heavy_tail"] = bench_heavy(a)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

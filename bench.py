@@ -74,7 +74,7 @@ GEN_LO = [1, 9, 17, 25, 33, 41, 49, 57]
 GEN_HI = [8, 16, 24, 32, 40, 48, 56, 63]
 
 
-def stage_work(stages, bucket_k, bucket_m, r):
+def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None):
     """Algorithmic FLOPs and HBM bytes of every stage.  Edge stages: series
     FMAs x 2 and 20 B per incidence (member id, gathered x, contribution);
     fused generic stages: the same summed over the buckets that no per-bucket
@@ -83,20 +83,24 @@ def stage_work(stages, bucket_k, bucket_m, r):
     reduction levels: per term the value read (8 B, plus its 2 B LDS slot at
     level 0), per chunk its 12 B descriptor and the 8 B result."""
     per_bucket = {s["size"] for s in stages if s["kind"] == 0}
+    if bucket_l is None:
+        bucket_l = [0] * len(bucket_k)
     out = []
     for s in stages:
         if s["kind"] == 0:
             k, m = s["size"], s["count"]
             out.append((2.0 * edge_fma(k, r) * m, edge_bytes(k) * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m)))
-        elif s["kind"] == 1:
+        elif s["kind"] in (1, 4):
             g = s["size"]
             f = b = 0.0
-            for k, m in zip(bucket_k, bucket_m):
+            for k, m, lanes in zip(bucket_k, bucket_m, bucket_l):
                 W = r - k + 1
-                if k >= 4 and k not in per_bucket and GEN_LO[g] <= W <= GEN_HI[g]:
+                if (k >= 4 and k not in per_bucket and GEN_LO[g] <= W <= GEN_HI[g]
+                        and (lanes > 0) == (s["kind"] == 4)):
                     f += 2.0 * edge_fma(k, r) * m
                     b += edge_bytes(k) * m
-            out.append((f, b, "generic edges W in [%d,%d], %d edges" % (GEN_LO[g], GEN_HI[g], s["count"])))
+            what = "generic" if s["kind"] == 1 else "lane-group"
+            out.append((f, b, "%s edges W in [%d,%d], %d edges" % (what, GEN_LO[g], GEN_HI[g], s["count"])))
         elif s["kind"] == 3:
             out.append((0.0, 20.0 * s["count"], "x into degree-rank order, n=%d" % s["count"]))
         else:
@@ -163,6 +167,8 @@ def stage_kernel(s, prec, r):
         return "edge_small<%s, %d, %d>" % (t, r - s["size"] + 1, SMALL_KIND[s["size"]]), (s["count"] + 255) // 256 * 256
     if s["kind"] == 1:
         return "edge_generic<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
+    if s["kind"] == 4:
+        return "edge_coop<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
     if s["kind"] == 2:
         if s["size"] == 0:
             return "reduce_level0", None
@@ -278,6 +284,7 @@ def _stage_rooflines(plan, xd, yd, r, nnz, reps):
     roofline."""
     from paper_2311_08595_amd import _lib as L
     bk, bm = plan.query(L.Q_BUCKET_K).tolist(), plan.query(L.Q_BUCKET_M).tolist()
+    bl = plan.query(L.Q_BUCKET_LANES).tolist()
     out = {}
     for prec in ("fp64", "fp32"):
         stages = stage_table(plan, xd, yd, prec, reps)
@@ -286,7 +293,7 @@ def _stage_rooflines(plan, xd, yd, r, nnz, reps):
             if st_["kind"] == 2:
                 st_["in_len"] = prev
                 prev = st_["count"]
-        work = stage_work(stages, bk, bm, r)
+        work = stage_work(stages, bk, bm, r, bl)
         best, roof = roofline_of(stages, work, prec, r, with_traffic=False)
         roof["avg_kernel_ms"] = best["ms"]
         roof["stages_ms_sum"] = sum(s_["ms"] for s_ in stages)
@@ -679,7 +686,8 @@ def main():
         plan.autotune(xd, reps=5)
         tune_s = time.perf_counter() - t0
         log("[bench] autotuned in %.2f s" % tune_s)
-    res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist()}
+    res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist(),
+           "bucket_l": plan.query(L.Q_BUCKET_LANES).tolist()}
     for prec in ("fp64", "fp32"):
         log("[bench] timing STTSV %s" % prec)
         dt = time_apply(prec) if tune_s is not None else untuned[prec]
@@ -723,7 +731,7 @@ def main():
     from paper_2311_08595_amd import _lib
     bk, bm = res["bucket_k"], res["bucket_m"]
     for prec in ("fp64", "fp32"):
-        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r)
+        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r, res["bucket_l"])
     best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64", r)
     roof["avg_kernel_ms"] = best["ms"]
     out["roofline"] = roof

@@ -139,7 +139,10 @@ int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t prec
  * edge-kernel launch of one size bucket
  * (kinds[s] = 0, sizes[s] = edge size k, counts[s] = edges in the bucket);
  * a fused launch of the generic kernel over several buckets (kinds[s] = 1,
- * sizes[s] = window-range index, counts[s] = edges covered); one level of
+ * sizes[s] = window-range index, counts[s] = edges covered); a fused launch
+ * of the lane-group kernel, where L lanes (a power of two >= |e|) share each
+ * edge of buckets with few edges and long series chains (kinds[s] = 4, sizes
+ * and counts as for kind 1); one level of
  * the node reduction (kinds[s] = 2, sizes[s] = level, counts[s] = chunks).
  * ms[s] = elapsed milliseconds of that stage.
  *   cap      capacity of the four host output arrays (entries)
@@ -441,6 +444,9 @@ int sttsv_mpnn_query(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, int32_t what, float
 #define STTSV_Q_CONTRIB    10  /* double[nnz] the per-incidence contributions of  */
                                /*            the last apply, in node-major order  */
                                /*            (synchronises the plan's stream)      */
+#define STTSV_Q_BUCKET_LANES 11 /* int64[nb] lanes per edge of each bucket's FP64 */
+                               /*            kernel (0: one lane per edge; else a  */
+                               /*            lane group, see sttsv_apply_timed)    */
 #define STTSV_Q_BUCKET_RUNS 9  /* int64[nb]  FP64 prefix-reuse runs of each bucket */
                                /*            (0: the bucket does not reuse; else */
                                /*            m - runs edges take a shared prefix) */

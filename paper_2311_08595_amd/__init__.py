@@ -210,7 +210,8 @@ class Plan:
         sizes = {_lib.Q_PERM: inf["m"], _lib.Q_MEM: inf["nnz"], _lib.Q_BUCKET_K: inf["nbuckets"],
                  _lib.Q_BUCKET_M: inf["nbuckets"], _lib.Q_TPTR: inf["n"] + 1,
                  _lib.Q_TSLOT: inf["nnz"], _lib.Q_BUCKET_R: inf["nbuckets"],
-                 _lib.Q_BUCKET_RUNS: inf["nbuckets"], _lib.Q_CONTRIB: inf["nnz"]}
+                 _lib.Q_BUCKET_RUNS: inf["nbuckets"], _lib.Q_BUCKET_LANES: inf["nbuckets"],
+                 _lib.Q_CONTRIB: inf["nnz"]}
         if what in (_lib.Q_WEIGHTS, _lib.Q_SCALE_EXP):
             sizes[what] = self.graph_info(0)["r"] + 1
         cnt = sizes[what]

@@ -31,7 +31,7 @@ PREC = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"fp64": 0, "fp32_fp64": 1}
 
 Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, Q_BUCKET_R, Q_BUCKET_RUNS, \
-    Q_CONTRIB = range(11)
+    Q_CONTRIB, Q_BUCKET_LANES = range(12)
 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed", "sttsv_apply_naive",

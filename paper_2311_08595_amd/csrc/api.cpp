@@ -232,13 +232,15 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
       case STTSV_Q_BUCKET_K:
       case STTSV_Q_BUCKET_M:
       case STTSV_Q_BUCKET_R:
-      case STTSV_Q_BUCKET_RUNS: {
+      case STTSV_Q_BUCKET_RUNS:
+      case STTSV_Q_BUCKET_LANES: {
         std::vector<int64_t> v;
         for (const auto& b : p.buckets)
-          v.push_back(what == STTSV_Q_BUCKET_K   ? b.k
-                      : what == STTSV_Q_BUCKET_M ? b.m
-                      : what == STTSV_Q_BUCKET_R ? b.r
-                                                 : (b.reuse ? b.desc[0].nruns : 0));
+          v.push_back(what == STTSV_Q_BUCKET_K      ? b.k
+                      : what == STTSV_Q_BUCKET_M    ? b.m
+                      : what == STTSV_Q_BUCKET_R    ? b.r
+                      : what == STTSV_Q_BUCKET_LANES ? b.coop[0]
+                                                    : (b.reuse ? b.desc[0].nruns : 0));
         return copy_out<int64_t, int64_t>(v, out, count);
       }
       case STTSV_Q_WEIGHTS:

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <utility>
 
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace sttsv {
@@ -24,6 +26,10 @@ void fill_edge_gen4(EdgeTables&);
 void fill_edge_gen5(EdgeTables&);
 void fill_edge_gen6(EdgeTables&);
 void fill_edge_gen7(EdgeTables&);
+void fill_edge_coop0(EdgeTables&);
+void fill_edge_coop1(EdgeTables&);
+void fill_edge_coop2(EdgeTables&);
+void fill_edge_coop3(EdgeTables&);
 
 namespace {
 
@@ -76,6 +82,10 @@ EdgeTables build_tables() {
   fill_edge_gen5(t);
   fill_edge_gen6(t);
   fill_edge_gen7(t);
+  fill_edge_coop0(t);
+  fill_edge_coop1(t);
+  fill_edge_coop2(t);
+  fill_edge_coop3(t);
   t.k1 = &launch_k1;
   return t;
 }
@@ -117,8 +127,15 @@ void assign_lanes(Plan& p) {
         const Bucket& B = p.buckets[S.index];
         c += edge_cost(B.k, B.r, B.m);
       } else if (S.type == 1) {
-        // the runtime-k kernel runs at about half the FMA rate of the others
-        for (int b : p.groups[S.index].buckets) c += 2.0 * edge_cost(p.buckets[b].k, p.buckets[b].r, p.buckets[b].m);
+        const GenGroup& G = p.groups[S.index];
+        for (int b : G.buckets) {
+          const Bucket& B = p.buckets[b];
+          const int L = B.coop[G.f64 ? 0 : 1];
+          if (G.coop)   // lane groups: 2 log2 L products per lane instead of 2(k-3) per edge
+            c += edge_cost(B.k, B.r, B.m) * 1.5 * std::log2((double)L) * L / std::max(1, 2 * (B.k - 3));
+          else          // the runtime-k kernel runs at about half the FMA rate of the others
+            c += 2.0 * edge_cost(B.k, B.r, B.m);
+        }
       } else {
         continue;
       }
@@ -197,7 +214,8 @@ static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, 
   }
   if (S.type == 1) {
     const GenGroup& G = p.groups[S.index];
-    const GenLaunchFn fn = G.f64 ? tab.gen64[G.range] : tab.gen32[G.range];
+    const GenLaunchFn fn = G.coop ? (G.f64 ? tab.coop64[G.range] : tab.coop32[G.range])
+                                  : (G.f64 ? tab.gen64[G.range] : tab.gen32[G.range]);
     return fn ? fn(c, G.d_bks, G.d_tasks, G.ntasks, G.lds, s) : hipErrorInvalidValue;
   }
   const size_t l = static_cast<size_t>(S.index);
@@ -298,6 +316,7 @@ void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t*
     *size = p.buckets[S.index].k;
     *count = p.buckets[S.index].m;
   } else if (S.type == 1) {
+    if (p.groups[S.index].coop) *kind = 4;
     *size = p.groups[S.index].range;
     int64_t m = 0;
     for (int b : p.groups[S.index].buckets) m += p.buckets[b].m;

@@ -35,6 +35,11 @@ constexpr int kGenLo[kGenRanges] = {1, 9, 17, 25, 33, 41, 49, 57};
 constexpr int kGenHi[kGenRanges] = {8, 16, 24, 32, 40, 48, 56, 63};
 constexpr int64_t kLdsBudget = 40 * 1024;  // LDS per generic block by default (>= 4 blocks per CU)
 constexpr int64_t kLdsMax = 64 * 1024;     // largest LDS per generic block the tuner may choose
+constexpr int kKrBytes = 1024;           // register-resident kernels by default only where (k-1) W sizeof(T) fits
+constexpr bool kr_default(int k, int W, int tsz) { return (k - 1) * W * tsz <= kKrBytes; }
+constexpr int kCoopBlock = 256;          // threads per block of the lane-group edge kernel
+constexpr int kCoopMaxW64 = 48;          // largest window of its FP64 variant (three series in registers)
+constexpr int kCoopMaxW32 = 63;          // ... and of its FP32 variant
 
 // Generic kernel: suffix checkpoint interval C for window W and series size
 // tsz bytes (C + 2 live series within about 160 VGPRs, at most 4), and the
@@ -73,6 +78,7 @@ struct BucketDesc {
   int32_t qexp;         // series scale exponent (rho = 2^qexp)
   int32_t lds_stack;    // generic kernel: 1 = stack in LDS
   int32_t reuse_emin;   // prefix reuse: smallest exponent of z_0, z_1 with an exact rescale
+  int32_t lanes;        // lane-group kernel: lanes per edge (power of two >= k, <= 64)
   double wk;            // w(e)/|beta(e)| (r-1)! for w(e) = |e|
   const double* wgt;    // per-edge w(e)/|beta(e)| (r-1)! (edge-weighted plans), or null
   // prefix reuse (FP64 register-resident kernels): runs of consecutive edges
@@ -99,8 +105,17 @@ struct EdgeTables {
   SmallLaunchFn run64[4][kMaxW + 1];     // prefix-reuse variants, k = 4..7, FP64
   GenLaunchFn gen64[kGenRanges];
   GenLaunchFn gen32[kGenRanges];
+  GenLaunchFn coop64[kGenRanges];        // fused lane-group kernels by window range (FP64, FP32 series)
+  GenLaunchFn coop32[kGenRanges];
   SmallLaunchFn k1;
 };
+
+// Lanes per edge of the lane-group kernel for edges of size k in an order-r
+// tensor (0: one lane per edge), given how many one-lane waves the graph's
+// edges of every size with the same window range would make.  A pure
+// function of the graph, so a graph's results do not depend on the plan it
+// is part of.
+int coop_lanes(int r, int k, int64_t range_waves);
 const EdgeTables& edge_tables();
 
 // One level of the deterministic node reduction.
@@ -141,6 +156,8 @@ struct Bucket {
   void* gstack[2] = {nullptr, nullptr};  // generic-kernel global stacks [fp64, fp32]
   BucketDesc desc[2];     // [fp64 series, fp32 series]
   int small_kind[2] = {-1, -1};          // SmallKind, or -1: generic / k = 1
+  int lanes_per_edge = 0;                // lane-group kernel: lanes per edge (0: not this kernel)
+  int coop[2] = {0, 0};                  // lanes per edge per series type (0 where W is above its cap)
   int lds_pref[2] = {-1, -1};            // generic stack placement: -1 auto, 0 global, 1 LDS
   bool reuse = false;                    // FP64 register-resident kernel with prefix reuse
   int reuse_pref = -1;                   // tuner choice: -1 flag decides, 0 off, 1 on
@@ -152,6 +169,7 @@ struct Bucket {
 // falls in one range.
 struct GenGroup {
   int range = 0;
+  bool coop = false;    // lane-group kernel (else the one-lane generic kernel)
   int seq = 0;          // launch sequence: 0 = FP64 apply, 1 = FP32-series apply
   bool f64 = true;      // series type of the group's kernels
   int64_t ntasks = 0;

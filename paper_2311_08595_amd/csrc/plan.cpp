@@ -404,6 +404,24 @@ bool connected_graph(const GraphIn& g, const std::vector<int64_t>& deg) {
 
 }  // namespace
 
+// Lane groups pay where one lane per edge leaves the chip idle: the one-lane
+// kernel runs an edge's 2(k-3) products one after another, with a dependent
+// gather, store and reload per member, a group of L lanes 2 log2(L) products
+// per lane.  They are taken for sizes k >= 8 whose chain shrinks by more than
+// the group's 1.5x shuffle and idle-lane cost, when all of the graph's edges
+// in the same window range would make fewer one-lane waves than half the
+// chip's SIMDs (else the fused one-lane launch keeps the chip busy and its
+// total work is lower).
+int coop_lanes(int r, int k, int64_t range_waves) {
+  constexpr int64_t kHalfSimds = 512;
+  (void)r;
+  if (k < 8 || k > 64) return 0;
+  int L = 8;
+  while (L < k) L <<= 1;
+  if (k - 3.0 <= 1.5 * std::log2((double)L)) return 0;
+  return range_waves < kHalfSimds ? L : 0;
+}
+
 // Fused generic launches: every bucket of size >= 4 without a per-bucket
 // kernel, grouped by (launch sequence, series type, window range).  Frees
 // and rebuilds the groups; stage lists must be rebuilt afterwards.
@@ -419,18 +437,49 @@ int build_groups(Plan& P) {
   for (int seq = 0; seq < 2; ++seq) {
     for (int rg = 0; rg < kGenRanges; ++rg) {
       for (int t = 0; t < 2; ++t) {
+       for (int cp = 0; cp < 2; ++cp) {
         GenGroup grp;
         grp.range = rg;
         grp.seq = seq;
         grp.f64 = t == 0;
+        grp.coop = cp == 1;
         for (size_t b = 0; b < P.buckets.size(); ++b) {
           const Bucket& B = P.buckets[b];
           const int type = (seq == 0 || !B.fp32_ok || B.k == 1) ? 0 : 1;
-          if (type != t || B.k < 4 || B.small_kind[t] >= 0) continue;
+          if (type != t || B.k < 4 || B.small_kind[t] >= 0 || (B.coop[t] > 0) != grp.coop) continue;
           if (gen_range_of(B.r - B.k + 1) != rg) continue;
           grp.buckets.push_back(static_cast<int>(b));
         }
         if (grp.buckets.empty()) continue;
+        if (grp.coop) {
+          // lane groups: the largest per-lane work (log2(L) W^2) first
+          std::stable_sort(grp.buckets.begin(), grp.buckets.end(), [&](int a, int b) {
+            const Bucket& A = P.buckets[a];
+            const Bucket& B = P.buckets[b];
+            const int64_t wa = (int64_t)A.coop[t] * (A.r - A.k + 1) * (A.r - A.k + 1);
+            const int64_t wb = (int64_t)B.coop[t] * (B.r - B.k + 1) * (B.r - B.k + 1);
+            return wa > wb;
+          });
+          std::vector<BucketDesc> bks;
+          std::vector<GenTask> tasks;
+          for (size_t q = 0; q < grp.buckets.size(); ++q) {
+            Bucket& B = P.buckets[grp.buckets[q]];
+            if (seq == 0 && t == 0) B.task0 = static_cast<int64_t>(tasks.size());
+            bks.push_back(B.desc[t]);
+            const int64_t per = kCoopBlock / B.coop[t];
+            const int64_t nblk = (B.m + per - 1) / per;
+            for (int64_t blk = 0; blk < nblk; ++blk)
+              tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
+          }
+          grp.ntasks = (int64_t)tasks.size();
+          P.groups.push_back(std::move(grp));
+          GenGroup& H = P.groups.back();
+          const int64_t before = P.device_bytes;
+          if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P.device_bytes)) != STTSV_OK) return rc;
+          if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P.device_bytes)) != STTSV_OK) return rc;
+          H.bytes = P.device_bytes - before;
+          continue;
+        }
         // longest per-edge work first, so the slow blocks start early
         std::stable_sort(grp.buckets.begin(), grp.buckets.end(), [&](int a, int b) {
           const Bucket& A = P.buckets[a];
@@ -473,6 +522,7 @@ int build_groups(Plan& P) {
         if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P.device_bytes)) != STTSV_OK) return rc;
         if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P.device_bytes)) != STTSV_OK) return rc;
         H.bytes = P.device_bytes - before;
+       }
       }
     }
   }
@@ -539,7 +589,9 @@ static void edge_dies(const Bucket& B, std::vector<uint8_t>& die) {
     return;
   }
   for (int64_t i = 0; i < B.m; ++i) {
-    if (B.k == 1 || B.small_kind[0] >= 0)
+    if (B.coop[0] > 0)
+      die[i] = static_cast<uint8_t>((B.task0 + i / (kCoopBlock / B.coop[0])) % kXcd);
+    else if (B.k == 1 || B.small_kind[0] >= 0)
       die[i] = static_cast<uint8_t>((i / kSmallBlock) % kXcd);
     else if (B.task0 >= 0)
       die[i] = static_cast<uint8_t>((B.task0 + i / kGenBlock) % kXcd);
@@ -631,36 +683,52 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     }
   }
 
-  // ---- buckets keyed by (r, k); every graph's edges of size k form a
-  // contiguous run of its bucket, in the graph's own canonical order
-  std::vector<std::vector<int64_t>> cnt_rk(rmax + 1, std::vector<int64_t>(rmax + 1, 0));
+  // ---- buckets keyed by (r, k, lanes per edge); every graph's edges of
+  // size k form a contiguous run of one bucket, in the graph's own canonical
+  // order.  The lanes per edge (one, or a lane group) follow from the graph's
+  // own edge count of that size, so each graph's results are those of its
+  // single-graph plan, whatever else is in the batch.
+  constexpr int kModes = 5;                       // lanes per edge: 1 (mode 0), 8, 16, 32, 64
+  auto mode_of = [](int L) { return L == 0 ? 0 : L == 8 ? 1 : L == 16 ? 2 : L == 32 ? 3 : 4; };
+  const int mode_lanes[kModes] = {0, 8, 16, 32, 64};
+  std::vector<std::vector<std::vector<int64_t>>> cnt(
+      rmax + 1, std::vector<std::vector<int64_t>>(rmax + 1, std::vector<int64_t>(kModes, 0)));
   std::vector<std::vector<int64_t>> goff(G, std::vector<int64_t>(rmax + 1, 0));
+  std::vector<std::vector<int>> gmode(G, std::vector<int>(rmax + 1, 0));
   for (int g = 0; g < G; ++g) {
     std::vector<int64_t> mk(gs[g].r + 1, 0);
     for (int64_t e = 0; e < gs[g].m; ++e) mk[gs[g].eptr[e + 1] - gs[g].eptr[e]]++;
+    std::vector<int64_t> rwaves(kGenRanges, 0);   // one-lane waves of the graph's sizes >= 4 per window range
+    for (int k = 4; k <= gs[g].r; ++k)
+      if (mk[k] > 0) rwaves[gen_range_of(gs[g].r - k + 1)] += (mk[k] + 63) / 64;
     for (int k = 1; k <= gs[g].r; ++k) {
-      goff[g][k] = cnt_rk[gs[g].r][k];
-      cnt_rk[gs[g].r][k] += mk[k];
+      const int md = k >= 4 && mk[k] > 0 ? mode_of(coop_lanes(gs[g].r, k, rwaves[gen_range_of(gs[g].r - k + 1)])) : 0;
+      gmode[g][k] = md;
+      goff[g][k] = cnt[gs[g].r][k][md];
+      cnt[gs[g].r][k][md] += mk[k];
     }
   }
-  std::vector<std::vector<int>> bidx(rmax + 1, std::vector<int>(rmax + 1, -1));
+  std::vector<std::vector<std::vector<int>>> bidx(rmax + 1,
+                                                  std::vector<std::vector<int>>(rmax + 1, std::vector<int>(kModes, -1)));
   {
     int64_t edge_off = 0, slot_off = 0;
     for (int r = 2; r <= rmax; ++r)
-      for (int k = 1; k <= r; ++k) {
-        if (cnt_rk[r][k] == 0) continue;
-        Bucket B;
-        B.r = r;
-        B.k = k;
-        B.m = cnt_rk[r][k];
-        B.edge_off = edge_off;
-        B.slot_off = slot_off;
-        if (k > 1) B.fp32_ok = fp32_scale(r, k, &B.qexp32);
-        bidx[r][k] = static_cast<int>(P->buckets.size());
-        P->buckets.push_back(B);
-        edge_off += B.m;
-        slot_off += (int64_t)k * B.m;
-      }
+      for (int k = 1; k <= r; ++k)
+        for (int md = 0; md < kModes; ++md) {
+          if (cnt[r][k][md] == 0) continue;
+          Bucket B;
+          B.r = r;
+          B.k = k;
+          B.m = cnt[r][k][md];
+          B.edge_off = edge_off;
+          B.slot_off = slot_off;
+          B.lanes_per_edge = mode_lanes[md];
+          if (k > 1) B.fp32_ok = fp32_scale(r, k, &B.qexp32);
+          bidx[r][k][md] = static_cast<int>(P->buckets.size());
+          P->buckets.push_back(B);
+          edge_off += B.m;
+          slot_off += (int64_t)k * B.m;
+        }
   }
 
   // ---- member slots, canonical permutation, graph ids, node-major lists
@@ -693,7 +761,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       for (int k = 1; k <= in.r; ++k) {
         const auto& ids = c.order[k];
         if (ids.empty()) continue;
-        const Bucket& B = P->buckets[bidx[in.r][k]];
+        const Bucket& B = P->buckets[bidx[in.r][k][gmode[g][k]]];
         const int64_t base = goff[g][k];
         for (size_t t = 0; t < ids.size(); ++t) {
           const int64_t e = ids[t];
@@ -898,10 +966,15 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       d.nruns = 0;
       for (int q = 0; q < kRunMax; ++q) d.run_cnt[q] = 0;
       const auto& small = t == 0 ? tab.small64 : tab.small32;
+      const auto& coop = t == 0 ? tab.coop64 : tab.coop32;
+      B.coop[t] = B.lanes_per_edge > 0 && W <= (t == 0 ? kCoopMaxW64 : kCoopMaxW32) && coop[gen_range_of(W)] != nullptr
+                      ? B.lanes_per_edge : 0;
+      d.lanes = B.coop[t];
       int kind = -1;
       if (B.k == 2) kind = SK_K2;
       if (B.k == 3) kind = SK_K3;
-      if (B.k >= 4 && B.k <= 7 && !(P->flags & STTSV_FLAG_GENERIC_ONLY) && small[SK_R4 + (B.k - 4)][W] != nullptr)
+      if (B.k >= 4 && B.k <= 7 && !(P->flags & STTSV_FLAG_GENERIC_ONLY) && small[SK_R4 + (B.k - 4)][W] != nullptr &&
+          kr_default(B.k, W, t == 0 ? 8 : 4))
         kind = SK_R4 + (B.k - 4);
       B.small_kind[t] = kind;
     }

@@ -171,6 +171,7 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
     const int W = B.r - B.k + 1;
     for (int t = 0; t < 2; ++t) {
       if (t == 1 && !B.fp32_ok) continue;
+      if (B.coop[t] > 0) continue;        // lane-group kernel: no bit-identical alternative
       const std::string key = key_of(t, B);
       Choice ch{-1, -1, -1};
       bool cached = false;

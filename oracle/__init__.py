@@ -22,6 +22,8 @@ Modules
                node-major incidence lists, written independently of the C++
                planner so the two can be compared bit for bit.
 ``mpnn_ref``   FP64 forward/backward of the warm-start message-passing net.
+``ccss_ref``   the CCSS forest (Sec. III) and Alg. 4's memoised STTSV over it.
+``sshopm_ref`` the full contraction B x^r and SS-HOPM Z-eigenpairs.
 
 Every function names the passage of the paper it follows.  Where the paper is
 silent or garbled the reading taken is stated in the docstring.

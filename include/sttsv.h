@@ -428,6 +428,47 @@ int sttsv_mpnn_warm_start(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, double* x0);
 #define STTSV_MQ_X0 11
 int sttsv_mpnn_query(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, int32_t what, float* out, int64_t count);
 
+/* ---- the CCSS forest and the memoised STTSV over it (Alg. 4) ---------- */
+
+typedef struct {
+    int32_t levels;        /* depth of the forest (longest path)                 */
+    int64_t nodes;         /* distinct path prefixes                             */
+    int64_t roots;         /* level-1 nodes                                      */
+    int64_t convolutions;  /* forest edges = nodes - roots: one truncated        */
+                           /* series product each per STTSV                      */
+    int64_t leaves;        /* special leaves: member slots of edges of size >= 2 */
+    int64_t device_bytes;  /* device memory the forest and its workspaces hold   */
+    double  build_ms;      /* host wall time of the construction                 */
+} sttsv_ccss_info;
+
+/*
+ * sttsv_ccss_build -- build the Compound CSS forest of the plan's hypergraph
+ * on the device (Sec. III): for every member u of every edge e of size >= 2
+ * the path e \ {u}, members in the plan's degree-rank order, is a
+ * root-to-level-(|e|-1) path; nodes are distinct prefixes, numbered per
+ * level in (parent, vertex rank) order; (e, u) is a special leaf of the
+ * node ending its path.  Built level by level with device radix sorts of
+ * (parent, vertex) keys.  Replaces an earlier forest of the plan.
+ *   info  host, nullable: sizes of the forest.
+ * Synchronous.  Errors: EINVAL (NULL plan), ENOTSUP (batched plan: the
+ * workspace windows follow one tensor order), ENOMEM, EHIP.
+ */
+int sttsv_ccss_build(sttsv_plan_t plan, sttsv_ccss_info* info);
+
+/*
+ * sttsv_apply_ccss -- y = B x^(r-1) by Alg. 4 over the forest (Sec. IV-B):
+ * one truncated product per forest edge, each prefix's workspace computed
+ * once and shared by every edge -- of any size -- whose member paths pass
+ * through it; a special leaf (e, u) adds w(e)/|beta(e)| (r-1)! times the
+ * coefficient of t^(r-1) in e^(x_u t) times its path's product.  FP64.
+ * x, y device double[n] (x != y); the plan's node reduction sums the leaf
+ * values, so y is bitwise reproducible (not bitwise equal to sttsv_apply's).
+ * Asynchronous on the plan's stream; shares the plan's contribution buffer
+ * with sttsv_apply.  Errors: EINVAL (NULL argument, x == y, no forest built),
+ * EHIP.
+ */
+int sttsv_apply_ccss(sttsv_plan_t plan, const double* x, double* y);
+
 /* ---- plan introspection (host copies; used to check the layout) ------- */
 #define STTSV_Q_PERM        0  /* int64[m]   input index of canonical edge c      */
 #define STTSV_Q_MEM         1  /* int64[nnz] member slots (original vertex ids)   */
@@ -447,6 +488,16 @@ int sttsv_mpnn_query(sttsv_mpnn_t net, sttsv_mpnn_graph_t g, int32_t what, float
 #define STTSV_Q_BUCKET_LANES 11 /* int64[nb] lanes per edge of each bucket's FP64 */
                                /*            kernel (0: one lane per edge; else a  */
                                /*            lane group, see sttsv_apply_timed)    */
+#define STTSV_Q_CCSS_LEVEL_N 12 /* int64[levels] nodes per level of the forest   */
+#define STTSV_Q_CCSS_VERT   13  /* int64[nodes] vertex id of every node, level by  */
+                                /*            level, in node order                 */
+#define STTSV_Q_CCSS_PARENT 14  /* int64[nodes] parent's index in the level above  */
+                                /*            (-1 on level 1)                      */
+#define STTSV_Q_CCSS_LEAF   15  /* int64[nnz] node (index in its level) owning the */
+                                /*            special leaf of every member slot    */
+                                /*            (slot order as STTSV_Q_MEM; -1 for   */
+                                /*            size-1 edges).  CCSS queries need a  */
+                                /*            built forest (EINVAL otherwise)      */
 #define STTSV_Q_BUCKET_RUNS 9  /* int64[nb]  FP64 prefix-reuse runs of each bucket */
                                /*            (0: the bucket does not reuse; else */
                                /*            m - runs edges take a shared prefix) */

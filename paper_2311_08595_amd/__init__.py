@@ -155,6 +155,28 @@ class Plan:
         _lib.check(fn(self._h, xp, yp, ctypes.byref(out)))
         return out.value, y
 
+    def ccss_build(self):
+        """Build the CCSS forest (Sec. III) on the device; returns its sizes."""
+        ci = _lib.CcssInfo()
+        _lib.check(self._lib.sttsv_ccss_build(self._h, ctypes.byref(ci)))
+        return dict(levels=ci.levels, nodes=ci.nodes, roots=ci.roots, convolutions=ci.convolutions,
+                    leaves=ci.leaves, device_bytes=ci.device_bytes, build_ms=ci.build_ms)
+
+    def apply_ccss(self, x, y=None):
+        """y = B x^(r-1) by Alg. 4 over the CCSS forest (FP64); returns y."""
+        import torch
+        xp = _dev_ptr(x, self.n, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        yp = _dev_ptr(y, self.n, "y")
+        _lib.check(self._lib.sttsv_apply_ccss(self._h, xp, yp))
+        return y
+
+    def ccss_query(self, what, count):
+        out = np.empty(count, dtype=np.int64)
+        _lib.check(self._lib.sttsv_plan_query(self._h, what, out.ctypes.data, count))
+        return out
+
     def zeig_sshopm(self, x0=None, alpha=1.0, tol=1e-12, max_iter=500, out=None, raise_on_notconv=True):
         """Z-eigenpair by the shifted power method (SS-HOPM, convex shift
         alpha >= 0).  Returns (x, info dict); x has 2-norm 1."""

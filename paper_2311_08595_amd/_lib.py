@@ -31,11 +31,11 @@ PREC = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"fp64": 0, "fp32_fp64": 1}
 
 Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, Q_BUCKET_R, Q_BUCKET_RUNS, \
-    Q_CONTRIB, Q_BUCKET_LANES = range(12)
+    Q_CONTRIB, Q_BUCKET_LANES, Q_CCSS_LEVEL_N, Q_CCSS_VERT, Q_CCSS_PARENT, Q_CCSS_LEAF = range(16)
 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed", "sttsv_apply_naive",
-           "sttsv_contract", "sttsv_contract_noalloc", "zeigvec_sshopm",
+           "sttsv_contract", "sttsv_contract_noalloc", "zeigvec_sshopm", "sttsv_ccss_build", "sttsv_apply_ccss",
            "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
            "sttsv_plan_graph_info", "sttsv_plan_autotune",
            "sttsv_mpnn_graph", "sttsv_mpnn_graph_destroy", "sttsv_mpnn_create", "sttsv_mpnn_destroy",
@@ -73,6 +73,12 @@ class PlanInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("graphs", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
+class CcssInfo(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("nodes", ctypes.c_int64), ("roots", ctypes.c_int64),
+                ("convolutions", ctypes.c_int64), ("leaves", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("build_ms", ctypes.c_double)]
+
+
 class GraphDesc(ctypes.Structure):
     _fields_ = [("eptr", ctypes.c_void_p), ("eidx", ctypes.c_void_p), ("m", ctypes.c_int64),
                 ("n", ctypes.c_int32), ("r", ctypes.c_int32), ("w", ctypes.c_void_p)]
@@ -101,6 +107,10 @@ def load(path=None):
     if not os.path.exists(path):
         raise RuntimeError("libsttsv.so not built: run python -m paper_2311_08595_amd.build "
                            "(no CPU fallback exists)")
+    # torch first: the library must bind to the HIP runtime torch loads (torch
+    # ships its own; loaded before it, the library would pull in another one,
+    # which torch would then share)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -110,6 +120,8 @@ def load(path=None):
     lib.sttsv_apply_naive.argtypes = [P, P, P]
     lib.sttsv_contract.argtypes = [P, P, P, P]
     lib.sttsv_contract_noalloc.argtypes = [P, P, P, P]
+    lib.sttsv_ccss_build.argtypes = [P, ctypes.POINTER(CcssInfo)]
+    lib.sttsv_apply_ccss.argtypes = [P, P, P]
     lib.zeigvec_sshopm.argtypes = [P, P, ctypes.c_double, ctypes.c_double, i32, P, P]
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]

@@ -150,6 +150,21 @@ int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out) {
   return guarded([&] { return sttsv::contract(*plan->p, x, y, out); });
 }
 
+int sttsv_ccss_build(sttsv_plan_t plan, sttsv_ccss_info* info) {
+  if (plan == nullptr || plan->p == nullptr) return STTSV_EINVAL;
+  return guarded([&] { return sttsv::build_ccss(*plan->p, info); });
+}
+
+int sttsv_apply_ccss(sttsv_plan_t plan, const double* x, double* y) {
+  if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr) return STTSV_EINVAL;
+  if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
+  if (plan->p->ccss == nullptr) return STTSV_EINVAL;
+  return guarded([&] {
+    Plan& p = *plan->p;
+    return sttsv::launch_ccss(p, x, y, p.stream) == hipSuccess ? STTSV_OK : STTSV_EHIP;
+  });
+}
+
 int sttsv_contract_noalloc(sttsv_plan_t plan, const double* x, double* y, double* out) {
   if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr || out == nullptr) return STTSV_EINVAL;
   if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;
@@ -245,6 +260,14 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
       }
       case STTSV_Q_WEIGHTS:
         return copy_out<double, double>(p.weights, out, count);
+      case STTSV_Q_CCSS_LEVEL_N:
+      case STTSV_Q_CCSS_VERT:
+      case STTSV_Q_CCSS_PARENT:
+      case STTSV_Q_CCSS_LEAF: {
+        std::vector<int64_t> v;
+        const int rc = sttsv::ccss_query(p, what, v);
+        return rc != STTSV_OK ? rc : copy_out<int64_t, int64_t>(v, out, count);
+      }
       case STTSV_Q_CONTRIB: {
         if (count != p.nnz) return STTSV_EINVAL;
         std::vector<double> c(p.nnz), v(p.nnz);

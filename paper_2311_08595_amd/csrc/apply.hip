@@ -197,6 +197,8 @@ static hipError_t launch_permute(Plan& p, const double* x, const int32_t* done, 
   return hipGetLastError();
 }
 
+hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s) { return launch_permute(p, x, nullptr, s); }
+
 // c.x: the caller's x for the permute stage, the rank-ordered copy for edge stages
 static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, double* y, hipStream_t s) {
   const EdgeTables& tab = edge_tables();

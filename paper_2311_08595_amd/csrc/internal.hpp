@@ -252,6 +252,8 @@ struct Plan {
 
   // solver scratch (allocated on first solve)
   struct Solver* solver = nullptr;
+  // the CCSS forest (built on request, ccss.hip)
+  struct CcssForest* ccss = nullptr;
 };
 
 // planner (plan.cpp): a plan over the disjoint union of G hypergraphs
@@ -294,6 +296,15 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
 hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
                              const int32_t* skip64, hipStream_t s);
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false);
+
+// x into degree-rank order (the copy the edge kernels gather from)
+hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s);
+
+// the CCSS forest and Alg. 4 over it (ccss.hip)
+int build_ccss(Plan& p, sttsv_ccss_info* info);
+hipError_t launch_ccss(Plan& p, const double* x, double* y, hipStream_t s);
+int ccss_query(const Plan& p, int32_t what, std::vector<int64_t>& out);
+void free_ccss(Plan& p);
 
 // reduction kernels (reduce.hip)
 hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,

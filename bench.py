@@ -536,6 +536,59 @@ def bench_batch(a):
     return res
 
 
+def coo_bytes(sizes, r):
+    """COO storage (4-byte indices, 8-byte values) of the hypergraph's
+    tensor: of its IOU non-zeros (one sorted index tuple per edge, Sec. III)
+    and of every non-zero of the order-r blowup tensor (|beta(e)| = |e|!
+    S(r,|e|) tuples of r indices per edge, Sec. II), the latter as log10."""
+    from math import factorial, log10
+    s2 = [[0] * (r + 1) for _ in range(r + 1)]
+    s2[0][0] = 1
+    for a_ in range(1, r + 1):
+        for b_ in range(1, a_ + 1):
+            s2[a_][b_] = b_ * s2[a_ - 1][b_] + s2[a_ - 1][b_ - 1]
+    ks, cnt = np.unique(sizes, return_counts=True)
+    iou = int(np.sum(cnt * (4 * ks + 8)))
+    blow = sum(int(c) * factorial(int(k)) * s2[r][int(k)] for k, c in zip(ks, cnt)) * (4 * r + 8)
+    return iou, log10(blow)
+
+
+def bench_ccss(plan, w, xd, yd, reps):
+    """Alg. 4 over the CCSS forest (Sec. III-IV) on the same plan: forest
+    sizes, storage against COO, construction time, FP64 STTSV time against
+    the leave-one-out kernels, and the largest relative difference."""
+    import torch
+    info = plan.ccss_build()
+    sizes = np.diff(w["eptr"])
+    iou, blow_log10 = coo_bytes(sizes, w["r"])
+    ccss_bytes = 8 * info["nodes"] + 4 * info["leaves"]
+    t_c = _timed_ccss(plan, xd, yd, reps)
+    y_c = yd.clone()
+    t_m = _timed_applies(plan, xd, yd, "fp64", 5, reps)
+    nz = yd != 0
+    naive_conv = int(np.sum(sizes * (sizes - 1)))
+    return dict(levels=info["levels"], nodes=info["nodes"], roots=info["roots"],
+                convolutions=info["convolutions"], leaves=info["leaves"],
+                convolutions_naive=naive_conv, convolutions_no_sharing=int(np.sum((sizes - 1) * (sizes + 2) // 2 - 2 * (sizes >= 2))),
+                build_ms=info["build_ms"], ccss_bytes=ccss_bytes, coo_iou_bytes=iou, coo_blowup_bytes_log10=blow_log10,
+                coo_iou_over_ccss=iou / ccss_bytes, coo_blowup_over_ccss_log10=blow_log10 - math.log10(ccss_bytes),
+                alg4_ms=t_c * 1e3, leave_one_out_ms=t_m * 1e3, alg4_over_leave_one_out=t_c / t_m,
+                max_rel_diff=float(((y_c[nz] - yd[nz]).abs() / yd[nz].abs()).max()),
+                workspace_device_bytes=info["device_bytes"])
+
+
+def _timed_ccss(plan, xd, yd, reps):
+    import torch
+    for _ in range(3):
+        plan.apply_ccss(xd, yd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.apply_ccss(xd, yd)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
 def bench_paper_synthetic(a):
     """The paper's synthetic sets S1-S4 (n=2500, m=25000, sizes 5, 10, ...,
     N_k for N_k = 30, 40, 50, 60, r = N_k): FP64 STTSV by the memoised
@@ -569,6 +622,7 @@ def bench_paper_synthetic(a):
                 return (time.perf_counter() - t0) / reps
             t_built = run(lambda x, y: p.apply(x, y, precision="fp64"))
             t_naive = run(p.apply_naive)
+            cc = bench_ccss(p, d, xd, yd, reps)
             if not a.no_tune:   # the same one-off tuning as the headline plan
                 p.autotune(xd, reps=5)
                 t_memo = run(lambda x, y: p.apply(x, y, precision="fp64"))
@@ -583,11 +637,13 @@ def bench_paper_synthetic(a):
                "memoised_hyperedges_per_s": m / t_memo, "naive_hyperedges_per_s": m / t_naive,
                "products_naive": int(np.sum(sizes * (sizes - 1))),
                "products_memoised": int(np.sum(np.where(sizes >= 4, 2 * (sizes - 3), (sizes == 3).astype(np.int64)))),
-               "naive_tflops": 2 * naive_fma / t_naive / 1e12, "memoised_tflops": 2 * memo_fma / t_memo / 1e12}
+               "naive_tflops": 2 * naive_fma / t_naive / 1e12, "memoised_tflops": 2 * memo_fma / t_memo / 1e12,
+               "ccss": cc}
         rows.append(row)
-        log("[bench]   %s (r=%d): memoised %.3f ms (as built %.3f), naive %.3f ms (%.1fx), naive %.1f TFLOP/s"
+        log("[bench]   %s (r=%d): memoised %.3f ms (as built %.3f), naive %.3f ms (%.1fx), naive %.1f TFLOP/s, "
+            "Alg. 4 over CCSS %.3f ms (%d nodes)"
             % (row["set"], r, row["memoised_ms"], row["memoised_as_built_ms"], row["naive_ms"], row["speedup"],
-               row["naive_tflops"]))
+               row["naive_tflops"], cc["alg4_ms"], cc["nodes"]))
     return rows
 
 
@@ -609,6 +665,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="time the plan as built, without autotuning")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--no-small", action="store_true", help="skip the small uniform workload (n=1e3, r=5)")
+    ap.add_argument("--no-ccss", action="store_true", help="skip the CCSS forest / Alg. 4 comparison")
     ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tail workload (n=2e5, r=50)")
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle worker processes (0: the host's share, <= 16)")
     ap.add_argument("--profile", choices=["zipf", "heavy", "small"], default=None,
@@ -742,6 +799,16 @@ def main():
     out["stages_fp64_ms"] = [(s["kind"], s["size"], s["count"], round(s["ms"], 5)) for s in res["fp64"]["stages"]]
     out["stages_fp32_ms"] = [(s["kind"], s["size"], s["count"], round(s["ms"], 5)) for s in res["fp32"]["stages"]]
     out["plan_s"] = plan_s
+    if not a.no_ccss:
+        log("[bench] CCSS forest and Alg. 4")
+        try:   # a failure here must not cost the headline line
+            out["ccss"] = bench_ccss(plan, w, xd, yd, 20)
+            log("[bench]   %d nodes, built in %.1f ms; Alg. 4 %.3f ms vs %.3f ms; COO(IOU)/CCSS %.2f"
+                % (out["ccss"]["nodes"], out["ccss"]["build_ms"], out["ccss"]["alg4_ms"],
+                   out["ccss"]["leave_one_out_ms"], out["ccss"]["coo_iou_over_ccss"]))
+        except Exception as exc:
+            out["ccss"] = {"error": str(exc)}
+            log("[bench]   CCSS failed: %s" % exc)
     plan.close()
 
     # prefix reuse (FP64, sizes 4..7): a plan with the flag; per-bucket share

@@ -24,6 +24,7 @@ Modules
 ``mpnn_ref``   FP64 forward/backward of the warm-start message-passing net.
 ``ccss_ref``   the CCSS forest (Sec. III) and Alg. 4's memoised STTSV over it.
 ``sshopm_ref`` the full contraction B x^r and SS-HOPM Z-eigenpairs.
+``cp_ref``     symmetric CP decomposition of B by Armijo gradient descent.
 
 Every function names the passage of the paper it follows.  Where the paper is
 silent or garbled the reading taken is stated in the docstring.

@@ -469,6 +469,55 @@ int sttsv_ccss_build(sttsv_plan_t plan, sttsv_ccss_info* info);
  */
 int sttsv_apply_ccss(sttsv_plan_t plan, const double* x, double* y);
 
+/* ---- symmetric CP decomposition of the blowup tensor (Sec. I) -------- */
+
+/* The model B ~ sum_l lambda_l a_l^(o r), l < R, fitted by least squares:
+ *   f(lambda, A) = ||B||^2 - 2 sum_l lambda_l B a_l^r
+ *                  + sum_{l,m} lambda_l lambda_m (a_l . a_m)^r,
+ *   df/dlambda_l = -2 B a_l^r + 2 sum_m lambda_m (a_l . a_m)^r,
+ *   df/da_l      = 2 r lambda_l (-B a_l^(r-1) + sum_m lambda_m (a_l . a_m)^(r-1) a_m).
+ * Each evaluation takes R STTSVs (FP64 series), the step Sec. I names as the
+ * bottleneck of this decomposition.  ||B||^2 sums W_S^2 / |beta(S)| over the
+ * distinct vertex sets S, W_S the summed weight of the edges on S. */
+#define STTSV_CP_MAX_R 32
+
+typedef struct {
+    int32_t iterations;   /* accepted steps                                  */
+    int32_t halvings;     /* step halvings over all iterations               */
+    double  f0;           /* objective at the start                          */
+    double  f;            /* objective at the end                            */
+    double  norm2;        /* ||B||^2                                         */
+} sttsv_cp_info;
+
+/*
+ * sttsv_cp_objective_grad -- f, df/dA and df/dlambda at (A, lambda).
+ *   R       1..STTSV_CP_MAX_R terms.
+ *   A       device double[R * n]: column l (a_l) at A + l n, vertex order.
+ *   lambda  device double[R].
+ *   f       host double: the objective.
+ *   dA      device double[R * n], same layout as A; dlambda device double[R].
+ * Inner products are summed in a fixed tree, so results are bitwise
+ * reproducible.  Synchronous (f is on the host on return); allocates a
+ * workspace of (R + R^2 + 256 (R^2 + R)) doubles per call.  Errors: EINVAL
+ * (NULL argument, R out of range), ENOTSUP (batched plan), ENOMEM, EHIP.
+ */
+int sttsv_cp_objective_grad(sttsv_plan_t plan, int32_t R, const double* A, const double* lambda, double* f,
+                            double* dA, double* dlambda);
+
+/*
+ * sym_cp_descent -- gradient descent on (lambda, A) with Armijo
+ * backtracking (the paper names the decomposition, not a method; this plain
+ * one is taken): with g the gradient and t the trial step (first: step),
+ * halve t until f(x - t g) <= f(x) - 1e-4 t ||g||^2 or 40 halvings were
+ * taken, accept x - t g, and start the next iteration from 2 t.
+ *   A, lambda  device, as above: the start on entry, the result on return.
+ *   iters      iterations (>= 0); step > 0.
+ *   info       host, nullable.
+ * Synchronous.  Errors: EINVAL, ENOTSUP (batched plan), ENOMEM, EHIP.
+ */
+int sym_cp_descent(sttsv_plan_t plan, int32_t R, double* A, double* lambda, int32_t iters, double step,
+                   sttsv_cp_info* info);
+
 /* ---- plan introspection (host copies; used to check the layout) ------- */
 #define STTSV_Q_PERM        0  /* int64[m]   input index of canonical edge c      */
 #define STTSV_Q_MEM         1  /* int64[nnz] member slots (original vertex ids)   */

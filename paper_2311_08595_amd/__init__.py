@@ -177,6 +177,34 @@ class Plan:
         _lib.check(self._lib.sttsv_plan_query(self._h, what, out.ctypes.data, count))
         return out
 
+    def _cp_args(self, A, lam):
+        import torch
+        if not isinstance(A, torch.Tensor) or A.dim() != 2 or A.shape[1] != self.n:
+            raise ValueError("A must be an R x n tensor (row l = a_l)")
+        R = A.shape[0]
+        return R, _dev_ptr(A.view(-1), R * self.n, "A"), _dev_ptr(lam, R, "lambda")
+
+    def cp_objective_grad(self, A, lam):
+        """Symmetric CP objective f(lambda, A) and its gradient (Sec. I):
+        A is R x n on the device (row l = a_l).  Returns (f, dA, dlambda)."""
+        import torch
+        R, ap, lp = self._cp_args(A, lam)
+        dA = torch.empty_like(A)
+        dl = torch.empty_like(lam)
+        f = ctypes.c_double()
+        _lib.check(self._lib.sttsv_cp_objective_grad(self._h, R, ap, lp, ctypes.byref(f),
+                                                     _dev_ptr(dA.view(-1), R * self.n, "dA"),
+                                                     _dev_ptr(dl, R, "dlambda")))
+        return f.value, dA, dl
+
+    def cp_descent(self, A, lam, iters, step=1.0):
+        """Armijo gradient descent on the symmetric CP objective, in place on
+        (A, lam); returns the info dict."""
+        R, ap, lp = self._cp_args(A, lam)
+        info = _lib.CpInfo()
+        _lib.check(self._lib.sym_cp_descent(self._h, R, ap, lp, int(iters), float(step), ctypes.byref(info)))
+        return dict(iterations=info.iterations, halvings=info.halvings, f0=info.f0, f=info.f, norm2=info.norm2)
+
     def zeig_sshopm(self, x0=None, alpha=1.0, tol=1e-12, max_iter=500, out=None, raise_on_notconv=True):
         """Z-eigenpair by the shifted power method (SS-HOPM, convex shift
         alpha >= 0).  Returns (x, info dict); x has 2-norm 1."""

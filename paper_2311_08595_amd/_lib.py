@@ -36,6 +36,7 @@ Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed", "sttsv_apply_naive",
            "sttsv_contract", "sttsv_contract_noalloc", "zeigvec_sshopm", "sttsv_ccss_build", "sttsv_apply_ccss",
+           "sttsv_cp_objective_grad", "sym_cp_descent",
            "heigvec_solve", "heigvec_solve_ex", "sttsv_plan_batch", "heigvec_solve_batch",
            "sttsv_plan_graph_info", "sttsv_plan_autotune",
            "sttsv_mpnn_graph", "sttsv_mpnn_graph_destroy", "sttsv_mpnn_create", "sttsv_mpnn_destroy",
@@ -77,6 +78,14 @@ class CcssInfo(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("nodes", ctypes.c_int64), ("roots", ctypes.c_int64),
                 ("convolutions", ctypes.c_int64), ("leaves", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("build_ms", ctypes.c_double)]
+
+
+class CpInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("halvings", ctypes.c_int32), ("f0", ctypes.c_double),
+                ("f", ctypes.c_double), ("norm2", ctypes.c_double)]
+
+
+CP_MAX_R = 32
 
 
 class GraphDesc(ctypes.Structure):
@@ -122,6 +131,8 @@ def load(path=None):
     lib.sttsv_contract_noalloc.argtypes = [P, P, P, P]
     lib.sttsv_ccss_build.argtypes = [P, ctypes.POINTER(CcssInfo)]
     lib.sttsv_apply_ccss.argtypes = [P, P, P]
+    lib.sttsv_cp_objective_grad.argtypes = [P, i32, P, P, P, P, P]
+    lib.sym_cp_descent.argtypes = [P, i32, P, P, i32, f64, ctypes.POINTER(CpInfo)]
     lib.zeigvec_sshopm.argtypes = [P, P, ctypes.c_double, ctypes.c_double, i32, P, P]
     lib.sttsv_apply_timed.argtypes = [P, P, P, i32, i32, P, P, P, P, P]
     lib.heigvec_solve.argtypes = [P, P, f64, P, ctypes.POINTER(SolveInfo)]

@@ -22,7 +22,7 @@ ARCH = os.environ.get("STTSV_ARCH", "gfx950")
 
 HIP_SOURCES = (["edge_part%d.hip" % i for i in range(8)] + ["edge_gen%d.hip" % i for i in range(8)]
                + ["edge_coop%d.hip" % i for i in range(4)]
-               + ["apply.hip", "reduce.hip", "nqz.hip", "mpnn.hip", "naive.hip", "sshopm.hip", "ccss.hip"])
+               + ["apply.hip", "reduce.hip", "nqz.hip", "mpnn.hip", "naive.hip", "sshopm.hip", "ccss.hip", "cp.hip"])
 CXX_SOURCES = ["plan.cpp", "api.cpp", "tune.cpp"]
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off"]
 

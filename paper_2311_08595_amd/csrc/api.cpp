@@ -165,6 +165,20 @@ int sttsv_apply_ccss(sttsv_plan_t plan, const double* x, double* y) {
   });
 }
 
+int sttsv_cp_objective_grad(sttsv_plan_t plan, int32_t R, const double* A, const double* lambda, double* f,
+                            double* dA, double* dlambda) {
+  if (plan == nullptr || plan->p == nullptr || A == nullptr || lambda == nullptr || f == nullptr || dA == nullptr ||
+      dlambda == nullptr)
+    return STTSV_EINVAL;
+  return guarded([&] { return sttsv::cp_objective_grad(*plan->p, R, A, lambda, f, dA, dlambda); });
+}
+
+int sym_cp_descent(sttsv_plan_t plan, int32_t R, double* A, double* lambda, int32_t iters, double step,
+                   sttsv_cp_info* info) {
+  if (plan == nullptr || plan->p == nullptr || A == nullptr || lambda == nullptr) return STTSV_EINVAL;
+  return guarded([&] { return sttsv::cp_descent(*plan->p, R, A, lambda, iters, step, info); });
+}
+
 int sttsv_contract_noalloc(sttsv_plan_t plan, const double* x, double* y, double* out) {
   if (plan == nullptr || plan->p == nullptr || x == nullptr || y == nullptr || out == nullptr) return STTSV_EINVAL;
   if (static_cast<const void*>(x) == static_cast<const void*>(y)) return STTSV_EINVAL;

@@ -201,6 +201,7 @@ struct GraphInfo {
   int32_t voff = 0;       // first vertex in the plan's vertex numbering
   int64_t eoff = 0;       // first input edge in the plan's edge numbering
   bool connected = false;
+  double norm2 = 0.0;     // ||B||^2 of the graph's blowup tensor
 };
 
 struct Plan {
@@ -305,6 +306,11 @@ int build_ccss(Plan& p, sttsv_ccss_info* info);
 hipError_t launch_ccss(Plan& p, const double* x, double* y, hipStream_t s);
 int ccss_query(const Plan& p, int32_t what, std::vector<int64_t>& out);
 void free_ccss(Plan& p);
+
+// symmetric CP decomposition of the blowup tensor over the STTSV (cp.hip)
+int cp_objective_grad(Plan& p, int32_t R, const double* A, const double* lambda, double* f, double* dA,
+                      double* dlambda);
+int cp_descent(Plan& p, int32_t R, double* A, double* lambda, int32_t iters, double step, sttsv_cp_info* info);
 
 // reduction kernels (reduce.hip)
 hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,

@@ -394,6 +394,37 @@ void canonicalise(const GraphIn& g, const std::vector<int64_t>& deg, Canon& c) {
   }
 }
 
+// ||B||^2 = sum over distinct vertex sets S of W_S^2 / |beta(S)| (Sec. II:
+// every entry of the blowup of S holds W_S / |beta(S)|, and edges on one
+// vertex set add to the same entries); |beta(S)| = |S|! S(r, |S|).  The
+// canonical order puts edges on one vertex set next to each other.
+double blowup_norm2(const GraphIn& g, const Canon& c) {
+  std::vector<std::vector<long double>> S(g.r + 1, std::vector<long double>(g.r + 1, 0.0L));
+  S[0][0] = 1.0L;
+  for (int a = 1; a <= g.r; ++a)
+    for (int b = 1; b <= a; ++b) S[a][b] = (long double)b * S[a - 1][b] + S[a - 1][b - 1];
+  long double tot = 0.0L, fact = 1.0L;
+  for (int k = 1; k <= g.r; ++k) {
+    fact *= (long double)k;
+    const long double beta = fact * S[g.r][k];
+    const auto& ids = c.order[k];
+    size_t t = 0;
+    while (t < ids.size()) {
+      long double W = 0.0L;
+      size_t u = t;
+      for (; u < ids.size(); ++u) {
+        if (u > t && !std::equal(c.rk.data() + g.eptr[ids[u]], c.rk.data() + g.eptr[ids[u]] + k,
+                                 c.rk.data() + g.eptr[ids[t]]))
+          break;
+        W += g.w != nullptr ? (long double)g.w[ids[u]] : (long double)k;
+      }
+      tot += W * W / beta;
+      t = u;
+    }
+  }
+  return static_cast<double>(tot);
+}
+
 bool connected_graph(const GraphIn& g, const std::vector<int64_t>& deg) {
   Dsu d(g.n);
   for (int64_t e = 0; e < g.m; ++e)
@@ -789,6 +820,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
         }
       }
       P->graphs[g].connected = connected_graph(in, degs[g]);
+      P->graphs[g].norm2 = blowup_norm2(in, c);
     }
   }
   P->connected = true;

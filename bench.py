@@ -127,33 +127,56 @@ def source_fingerprint():
     return h.hexdigest()[:16]
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sttsv_zipf_n1e6_m5e6_r25_traffic.md")
+PROFILE_STEMS = {"zipf": "sttsv_zipf_n1e6_m5e6_r25", "heavy": "sttsv_heavytail_n2e5_m2e6_r50"}
 
 
-def measured_traffic(kernel, grid):
-    """Calibrated HBM bytes per dispatch of (kernel, grid) from the committed
-    counter summary, or None when there is none for this kernel or the
-    sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_rows(workload, kind, ncells, value_cells):
+    """Rows {(kernel, grid or None): [values]} of a committed counter summary
+    (profiles/<workload>_<kind>.md), or None when it is missing or was taken
+    on other kernel sources (its fingerprint differs)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (PROFILE_STEMS.get(workload, "-"), kind))
+    if not os.path.exists(path):
         return None
     fp = None
     rows = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if line.startswith("source fingerprint:"):
                 fp = line.split(":", 1)[1].strip().strip("`")
             cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
-            if len(cells) == 6 and (cells[1].isdigit() or cells[1] == "-"):
+            if len(cells) == ncells and (cells[1].isdigit() or cells[1] == "-"):
                 try:
-                    rows[(cells[0], int(cells[1]) if cells[1] != "-" else None)] = float(cells[5])
+                    rows[(cells[0], int(cells[1]) if cells[1] != "-" else None)] = [float(cells[i])
+                                                                                      for i in value_cells]
                 except ValueError:
                     pass
-    if fp != source_fingerprint():
+    return rows if fp == source_fingerprint() else None
+
+
+def _lookup(rows, kernel, grid):
+    if rows is None:
         return None
     v = rows.get((kernel, grid))
+    return v if v is not None else rows.get((kernel, None))
+
+
+def measured_traffic(kernel, grid, workload="zipf"):
+    """Calibrated HBM bytes per dispatch of (kernel, grid) from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None (no summary for this kernel, or
+    the sources changed since the counters were taken)."""
+    v = _lookup(_profile_rows(workload, "traffic", 6, [5]), kernel, grid)
+    return None if v is None else v[0] * 1e6
+
+
+def measured_valu(kernel, grid, workload="zipf"):
+    """VALU and occupancy counters of (kernel, grid) from the committed
+    summary (or None): wave count, FP64 and FP32 FMA wave-instructions,
+    VALUBusy %, occupancy % and mean resident waves per CU."""
+    v = _lookup(_profile_rows(workload, "valu_occupancy", 13, [3, 7, 8, 10, 11, 12]), kernel, grid)
     if v is None:
-        v = rows.get((kernel, None))
-    return None if v is None else v * 1e6
+        return None
+    return dict(waves=v[0], fma64_instr=v[1], fma32_instr=v[2], valu_busy_pct=v[3], occupancy_pct=v[4],
+                waves_per_cu=v[5])
 
 
 SMALL_KIND = {2: 0, 3: 1, 4: 2, 5: 3, 6: 4, 7: 5}
@@ -178,20 +201,32 @@ def stage_kernel(s, prec, r):
     return None, None
 
 
-def roofline_of(stages, work, prec, r, with_traffic=True):
-    """Dominant stage and its roofline figures."""
+def roofline_of(stages, work, prec, r, workload=None):
+    """Dominant stage and its roofline figures; with a workload whose counter
+    summaries are committed, also the measured traffic and VALU counters of
+    the dominant kernel."""
     i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
     t = stages[i]["ms"] * 1e-3
     flops, byts, name = work[i]
     peak_f = PEAK_FP64_VALU      # FP64 FMA and non-packed FP32 FMA issue at the same rate
     kname, grid = stage_kernel(stages[i], prec, r)
-    traffic = measured_traffic(kname, grid) if kname and with_traffic else None
+    traffic = measured_traffic(kname, grid, workload) if kname and workload else None
     if flops / peak_f >= byts / PEAK_HBM:
-        return stages[i], dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
-                               frac=(flops / t) / peak_f, traffic=traffic, kernel=name)
-    return stages[i], dict(bound="hbm", achieved=byts / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                           frac=(byts / t) / PEAK_HBM, traffic=traffic, kernel=name,
-                           algorithmic_bytes=byts)
+        roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
+                    frac=(flops / t) / peak_f, traffic=traffic, kernel=name, profiled_kernel=kname)
+    else:
+        roof = dict(bound="hbm", achieved=byts / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                    frac=(byts / t) / PEAK_HBM, traffic=traffic, kernel=name, profiled_kernel=kname,
+                    algorithmic_bytes=byts)
+    cnt = measured_valu(kname, grid, workload) if kname and workload else None
+    if cnt is not None:
+        # FMA wave-instructions x 64 lanes x 2: the issued FLOPs (masked lanes
+        # included), over this run's kernel time, against the same peak
+        issued = (cnt["fma64_instr"] + cnt["fma32_instr"]) * 128.0
+        cnt["issued_flop"] = issued
+        cnt["issued_frac"] = issued / t / peak_f
+        roof["counters"] = cnt
+    return stages[i], roof
 
 
 def _oracle_terms(args):
@@ -279,7 +314,7 @@ def _timed_applies(plan, xd, yd, prec, warmup, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def _stage_rooflines(plan, xd, yd, r, nnz, reps):
+def _stage_rooflines(plan, xd, yd, r, nnz, reps, workload=None):
     """Per precision: the stage table of one apply and the dominant stage's
     roofline."""
     from paper_2311_08595_amd import _lib as L
@@ -294,7 +329,7 @@ def _stage_rooflines(plan, xd, yd, r, nnz, reps):
                 st_["in_len"] = prev
                 prev = st_["count"]
         work = stage_work(stages, bk, bm, r, bl)
-        best, roof = roofline_of(stages, work, prec, r, with_traffic=False)
+        best, roof = roofline_of(stages, work, prec, r, workload)
         roof["avg_kernel_ms"] = best["ms"]
         roof["stages_ms_sum"] = sum(s_["ms"] for s_ in stages)
         out[prec] = dict(roofline=roof, stages_ms=[(s_["kind"], s_["size"], s_["count"], round(s_["ms"], 5))
@@ -392,7 +427,7 @@ def bench_heavy(a):
                 y64 = yd.clone()
         nz = y64 != 0
         res["fp32_max_rel_err_vs_fp64"] = float(((yd[nz] - y64[nz]).abs() / y64[nz].abs()).max())
-        res.update(_stage_rooflines(p, xd, yd, r, len(w["eidx"]), 5))
+        res.update(_stage_rooflines(p, xd, yd, r, len(w["eidx"]), 5, "heavy"))
     log("[bench]   heavy tail: FP64 %.3f ms, FP32 %.3f ms per STTSV" % (res["sttsv_fp64_ms"], res["sttsv_fp32_ms"]))
     e2, i2, n2, _ = wl.largest_component(w["eptr"], w["eidx"], n)
     solve = {"n_lcc": n2, "m_lcc": len(e2) - 1, "tol": 1e-8}
@@ -414,30 +449,50 @@ def bench_heavy(a):
 
 
 def profile_apply(a):
-    """Short run for counter collection: plan as built, a few applies of each
-    precision on one workload."""
+    """Short run for a profiler: the plan autotuned as the headline run does
+    it (unless --no-tune), then a plain device copy that marks the end of
+    set-up (and, of known size, calibrates FETCH_SIZE / WRITE_SIZE), a few
+    applies of each precision, and the stage-timed passes whose HIP-event
+    times the profiler's averages are checked against."""
     import torch
     import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib as L
     from paper_2311_08595_amd import workloads as wl
     w = {"zipf": lambda: wl.zipf_powerlaw(n=a.n, m=a.m), "heavy": wl.heavy_tail,
          "small": wl.small_uniform}[a.profile]()
     with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as p:
         xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
         yd = torch.empty_like(xd)
-        if a.calib_copy_mib:
-            # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
-            # calibrate the counters taken on the STTSV kernels of the same run
-            src = torch.ones(a.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
-            dst = torch.empty_like(src)
-            torch.cuda.synchronize()
-            dst.copy_(src)
-            torch.cuda.synchronize()
-            del src, dst
+        if not a.no_tune:
+            # --tune-cache: later profiler passes reuse the first pass's
+            # kernel choices (counter collection slows launches unevenly)
+            p.autotune(xd, reps=5, cache_path=a.tune_cache)
+        mib = a.calib_copy_mib or 256
+        src = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[profile] %s: set-up done, %d MiB marker copy" % (w["name"], mib))
+        bk, bm, bl = p.query(L.Q_BUCKET_K), p.query(L.Q_BUCKET_M), p.query(L.Q_BUCKET_LANES)
         for prec in ("fp64", "fp32"):
             for _ in range(a.steps):
                 p.apply(xd, yd, precision=prec)
             torch.cuda.synchronize()
-            log("[profile] %s: %d applies of %s done" % (w["name"], a.steps, prec))
+            stages = stage_table(p, xd, yd, prec, a.stage_reps)
+            prev = len(w["eidx"])
+            for st_ in stages:
+                if st_["kind"] == 2:
+                    st_["in_len"] = prev
+                    prev = st_["count"]
+            work = stage_work(stages, bk, bm, w["r"], bl)
+            i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
+            kname, grid = stage_kernel(stages[i], prec, w["r"])
+            log("[profile] %s %s: %d applies, %d stage-timed passes; dominant stage %s (kernel %s, grid %s): "
+                "%.2f us by HIP events, %.4g FLOP, %.4g B algorithmic"
+                % (w["name"], prec, a.steps, a.stage_reps, work[i][2], kname, grid, stages[i]["ms"] * 1e3,
+                   work[i][0], work[i][1]))
 
 
 def bench_batch(a):
@@ -670,6 +725,7 @@ def main():
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle worker processes (0: the host's share, <= 16)")
     ap.add_argument("--profile", choices=["zipf", "heavy", "small"], default=None,
                     help="only run --steps applies of each precision on one workload (for counter runs)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner choice file (read, then appended to)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     a = ap.parse_args()
@@ -789,10 +845,10 @@ def main():
     bk, bm = res["bucket_k"], res["bucket_m"]
     for prec in ("fp64", "fp32"):
         res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r, res["bucket_l"])
-    best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64", r)
+    best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64", r, "zipf")
     roof["avg_kernel_ms"] = best["ms"]
     out["roofline"] = roof
-    best32, roof32 = roofline_of(res["fp32"]["stages"], res["fp32"]["work"], "fp32", r)
+    best32, roof32 = roofline_of(res["fp32"]["stages"], res["fp32"]["work"], "fp32", r, "zipf")
     roof32["avg_kernel_ms"] = best32["ms"]
     out["fp32_series"] = {"value": m / (res["fp32"]["ms"] * 1e-3), "ms_per_step": res["fp32"]["ms"],
                           "max_rel_err_vs_fp64": fp32_err, "roofline": roof32}

@@ -967,6 +967,20 @@ def main():
                 log("[bench]   SS-HOPM Z-eigenpair: %.4f s, %d updates (%.3f ms each), residual/lambda %.1e"
                     % (dt, zi["iterations"], dt * 1e3 / max(zi["iterations"], 1),
                        zi["residual"] / zi["lambda_"] if zi["lambda_"] else float("nan")))
+                # cost of one update against one STTSV of the same plan: fixed
+                # update counts (tol = 0), the difference over the extra updates
+                def zt(k):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    p2.zeig_sshopm(None, alpha=lam0, tol=0.0, max_iter=k, raise_on_notconv=False)
+                    return time.perf_counter() - t
+                zt(8)
+                t8, t40 = min(zt(8) for _ in range(3)), min(zt(40) for _ in range(3))
+                y2 = torch.empty_like(x1)
+                st_ms = _timed_applies(p2, x1, y2, "fp64", 5, 50) * 1e3
+                solve["sshopm_fp64"].update(update_ms=(t40 - t8) * 1e3 / 32, sttsv_ms=st_ms)
+                log("[bench]   SS-HOPM update %.3f ms against one FP64 STTSV %.3f ms"
+                    % ((t40 - t8) * 1e3 / 32, st_ms))
             except Exception as exc:
                 solve["sshopm_fp64"] = {"error": str(exc)}
                 log("[bench]   SS-HOPM failed: %s" % exc)

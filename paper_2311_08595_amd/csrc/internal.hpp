@@ -255,6 +255,8 @@ struct Plan {
   struct Solver* solver = nullptr;
   // the CCSS forest (built on request, ccss.hip)
   struct CcssForest* ccss = nullptr;
+  // SS-HOPM / contraction scratch and captured updates (first use, sshopm.hip)
+  struct ZState* zstate = nullptr;
 };
 
 // planner (plan.cpp): a plan over the disjoint union of G hypergraphs
@@ -306,6 +308,7 @@ int build_ccss(Plan& p, sttsv_ccss_info* info);
 hipError_t launch_ccss(Plan& p, const double* x, double* y, hipStream_t s);
 int ccss_query(const Plan& p, int32_t what, std::vector<int64_t>& out);
 void free_ccss(Plan& p);
+void free_zstate(Plan& p);
 
 // symmetric CP decomposition of the blowup tensor over the STTSV (cp.hip)
 int cp_objective_grad(Plan& p, int32_t R, const double* A, const double* lambda, double* f, double* dA,

@@ -273,6 +273,7 @@ int upload(T** dptr, const T* src, size_t count, int64_t* acct) {
 void free_plan(Plan* p) {
   if (p == nullptr) return;
   free_solver(*p);
+  free_zstate(*p);
   free_ccss(*p);
   (void)hipFree(p->d_mem);
   (void)hipFree(p->d_rid);

@@ -11,6 +11,7 @@
 // fixed tree, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 
@@ -88,18 +89,12 @@ __global__ void __launch_bounds__(kZBlock) z_fill(double* __restrict__ x, int64_
 }
 
 struct ZScratch {
-  double* y = nullptr;
-  double* part = nullptr;
-  double* st = nullptr;
-  ~ZScratch() {
-    if (y) (void)hipFree(y);
-    if (part) (void)hipFree(part);
-    if (st) (void)hipFree(st);
-  }
+  double* part = nullptr;   // 3 kZGrid block partials
+  double* st = nullptr;     // the three totals
 };
 
 // st[0..2] for (x, y, alpha), copied to host h[0..2] (synchronises the stream)
-hipError_t reduce3(const double* x, const double* y, int64_t n, double alpha, ZScratch& z, hipStream_t s,
+hipError_t reduce3(const double* x, const double* y, int64_t n, double alpha, const ZScratch& z, hipStream_t s,
                    double* h) {
   hipLaunchKernelGGL(z_stage, dim3(kZGrid), dim3(kZBlock), 0, s, x, y, n, alpha, z.part);
   hipLaunchKernelGGL(z_final, dim3(1), dim3(kZBlock), 0, s, (const double*)z.part, z.st);
@@ -113,11 +108,169 @@ unsigned vgrid(int64_t n) { return static_cast<unsigned>((n + kZBlock - 1) / kZB
 
 }  // namespace
 
+// Per-plan SS-HOPM state, allocated on first use and kept until the plan is
+// destroyed: the iterate, B x^(r-1), reduction partials, a device control
+// block with its pinned host mirror, and the captured graph of kZSteps updates.
+struct ZCtrl {
+  double lam;        // lambda at the current iterate
+  double alpha;      // shift
+  double tol;        // stopping tolerance (0: run max_iter updates)
+  int32_t iter;      // updates taken
+  int32_t max_iter;
+  int32_t done;      // no further update (converged, max_iter or numeric stop)
+  int32_t conv;
+  int32_t status;    // STTSV_OK or STTSV_ENUMERIC
+  int32_t pad;
+};
+
+struct ZState {
+  double* x = nullptr;
+  double* y = nullptr;
+  double* part = nullptr;
+  double* st = nullptr;
+  ZCtrl* ctrl = nullptr;
+  ZCtrl* hctrl = nullptr;
+  hipStream_t s = nullptr;      // own stream: the caller's may be the null stream, which cannot be captured
+  hipGraphExec_t exec = nullptr;
+};
+
+constexpr int kZSteps = 8;   // updates per captured graph
+
+namespace {
+
+// The control step after each update's reductions (one thread): lambda, the
+// stopping test, and the numeric check the next update needs (||w|| > 0).
+__global__ void z_check(const double* __restrict__ st, ZCtrl* __restrict__ c) {
+  if (c->done) return;
+  const double lam = st[0];
+  c->iter += 1;
+  const bool conv = c->tol > 0.0 && fabs(lam - c->lam) <= c->tol * fabs(lam);
+  c->lam = lam;
+  if (conv) {
+    c->conv = 1;
+    c->done = 1;
+  } else if (c->iter >= c->max_iter) {
+    c->done = 1;
+  } else if (!(st[1] > 0.0) || !isfinite(st[1])) {
+    c->status = STTSV_ENUMERIC;
+    c->done = 1;
+  }
+}
+
+// The control block at the start: lambda_0 from the first reduction.
+__global__ void z_ctrl_init(const double* __restrict__ st, ZCtrl* __restrict__ c, double alpha, double tol,
+                            int32_t max_iter) {
+  c->lam = st[0];
+  c->alpha = alpha;
+  c->tol = tol;
+  c->iter = 0;
+  c->max_iter = max_iter;
+  c->conv = 0;
+  c->status = STTSV_OK;
+  c->done = max_iter <= 0 ? 1 : 0;
+  if (!c->done && (!(st[1] > 0.0) || !isfinite(st[1]))) {
+    c->status = STTSV_ENUMERIC;
+    c->done = 1;
+  }
+}
+
+// z_stage / z_final / z_update gated by the control block, shift read from it
+__global__ void __launch_bounds__(kZBlock) z_stage_c(const double* x, const double* y, int64_t n,
+                                                     const ZCtrl* __restrict__ c, double* __restrict__ part) {
+  if (c->done) return;
+  __shared__ double sh[3][kZBlock];
+  const double alpha = c->alpha;
+  double a = 0.0, b = 0.0, d = 0.0;
+  for (int64_t v = blockIdx.x * (int64_t)kZBlock + threadIdx.x; v < n; v += (int64_t)kZGrid * kZBlock) {
+    const double xv = x[v], yv = y[v];
+    const double w = yv + alpha * xv;
+    a += xv * yv;
+    b += w * w;
+    d += yv * yv;
+  }
+  const int t = threadIdx.x;
+  sh[0][t] = a;
+  sh[1][t] = b;
+  sh[2][t] = d;
+  for (int s = kZBlock / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if (t < s) {
+      sh[0][t] += sh[0][t + s];
+      sh[1][t] += sh[1][t + s];
+      sh[2][t] += sh[2][t + s];
+    }
+  }
+  if (t == 0) {
+    part[3 * blockIdx.x + 0] = sh[0][0];
+    part[3 * blockIdx.x + 1] = sh[1][0];
+    part[3 * blockIdx.x + 2] = sh[2][0];
+  }
+}
+
+__global__ void __launch_bounds__(kZBlock) z_final_c(const double* __restrict__ part, const ZCtrl* __restrict__ c,
+                                                     double* __restrict__ st) {
+  if (c->done) return;
+  __shared__ double sh[3][kZBlock];
+  const int t = threadIdx.x;
+  for (int q = 0; q < 3; ++q) sh[q][t] = part[3 * t + q] + part[3 * (t + kZBlock) + q];
+  for (int s = kZBlock / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if (t < s)
+      for (int q = 0; q < 3; ++q) sh[q][t] += sh[q][t + s];
+  }
+  if (t == 0)
+    for (int q = 0; q < 3; ++q) st[q] = sh[q][0];
+}
+
+__global__ void __launch_bounds__(kZBlock) z_update_c(double* x, const double* y, int64_t n,
+                                                      const double* __restrict__ st, const ZCtrl* __restrict__ c) {
+  if (c->done) return;
+  const int64_t v = blockIdx.x * (int64_t)kZBlock + threadIdx.x;
+  if (v >= n) return;
+  x[v] = (y[v] + c->alpha * x[v]) / sqrt(st[1]);
+}
+
+}  // namespace
+
+void free_zstate(Plan& p) {
+  ZState* z = p.zstate;
+  if (z == nullptr) return;
+  if (z->exec) (void)hipGraphExecDestroy(z->exec);
+  for (void* q : {(void*)z->x, (void*)z->y, (void*)z->part, (void*)z->st, (void*)z->ctrl}) (void)hipFree(q);
+  if (z->hctrl) (void)hipHostFree(z->hctrl);
+  if (z->s) (void)hipStreamDestroy(z->s);
+  delete z;
+  p.zstate = nullptr;
+}
+
+static int get_zstate(Plan& p, ZState** out) {
+  if (p.zstate == nullptr) {
+    ZState* z = new ZState();
+    p.zstate = z;
+    const int64_t n = p.n;
+    if (hipMalloc(&z->x, std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&z->y, std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&z->part, 3 * kZGrid * sizeof(double)) != hipSuccess ||
+        hipMalloc(&z->st, 4 * sizeof(double)) != hipSuccess || hipMalloc(&z->ctrl, sizeof(ZCtrl)) != hipSuccess ||
+        hipHostMalloc(&z->hctrl, sizeof(ZCtrl), hipHostMallocDefault) != hipSuccess) {
+      free_zstate(p);
+      return STTSV_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&z->s, hipStreamNonBlocking) != hipSuccess) {
+      free_zstate(p);
+      return STTSV_EHIP;
+    }
+    p.device_bytes += (2 * n + 3 * kZGrid + 4) * (int64_t)sizeof(double) + (int64_t)sizeof(ZCtrl);
+  }
+  *out = p.zstate;
+  return STTSV_OK;
+}
+
 int contract(Plan& p, const double* x, double* y, double* out) {
-  ZScratch z;
-  if (hipMalloc(&z.part, 3 * kZGrid * sizeof(double)) != hipSuccess ||
-      hipMalloc(&z.st, 4 * sizeof(double)) != hipSuccess)
-    return STTSV_ENOMEM;
+  ZState* zs = nullptr;
+  const int rc = get_zstate(p, &zs);
+  if (rc != STTSV_OK) return rc;
+  ZScratch z{zs->part, zs->st};
   hipStream_t s = p.stream;
   if (launch_sttsv(p, x, y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
   double h[3];
@@ -161,66 +314,99 @@ int contract_noalloc(Plan& p, const double* x, double* y, double* out) {
   static_assert(3 * kZGrid + 3 <= kScratchDoubles, "contraction scratch exceeds the static array");
   hipStream_t s = p.stream;
   if (launch_sttsv(p, x, y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
-  ZScratch z;
-  z.part = sp;
-  z.st = sp + 3 * kZGrid;
+  ZScratch z{sp, sp + 3 * kZGrid};
   double h[3];
-  const hipError_t e = reduce3(x, y, p.n, 0.0, z, s, h);
-  z.part = nullptr;                                       // not owned: keep ~ZScratch from freeing it
-  z.st = nullptr;
-  if (e != hipSuccess) return STTSV_EHIP;
+  if (reduce3(x, y, p.n, 0.0, z, s, h) != hipSuccess) return STTSV_EHIP;
   *out = h[0];
   return STTSV_OK;
+}
+
+// One update: x <- (y + alpha x)/||.||, y = B x^(r-1), the three sums, the
+// control step.  Every kernel (the STTSV's through its done flag) does nothing
+// once the control block says done.
+static hipError_t enqueue_update(Plan& p, ZState& z, hipStream_t s) {
+  const int64_t n = p.n;
+  hipLaunchKernelGGL(z_update_c, dim3(vgrid(n)), dim3(kZBlock), 0, s, z.x, (const double*)z.y, n,
+                     (const double*)z.st, (const ZCtrl*)z.ctrl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_sttsv(p, z.x, z.y, STTSV_PREC_FP64, &z.ctrl->done, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(z_stage_c, dim3(kZGrid), dim3(kZBlock), 0, s, (const double*)z.x, (const double*)z.y, n,
+                     (const ZCtrl*)z.ctrl, z.part);
+  hipLaunchKernelGGL(z_final_c, dim3(1), dim3(kZBlock), 0, s, (const double*)z.part, (const ZCtrl*)z.ctrl, z.st);
+  hipLaunchKernelGGL(z_check, dim3(1), dim3(1), 0, s, (const double*)z.st, z.ctrl);
+  return hipGetLastError();
 }
 
 int zeig_sshopm(Plan& p, const double* x0, double alpha, double tol, int32_t max_iter, double* x,
                 sttsv_zeig_info* info) {
   const int64_t n = p.n;
-  ZScratch z;
-  if (hipMalloc(&z.y, n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&z.part, 3 * kZGrid * sizeof(double)) != hipSuccess ||
-      hipMalloc(&z.st, 4 * sizeof(double)) != hipSuccess)
-    return STTSV_ENOMEM;
-  hipStream_t s = p.stream;
+  ZState* zp = nullptr;
+  int rc = get_zstate(p, &zp);
+  if (rc != STTSV_OK) return rc;
+  ZState& z = *zp;
+  ZScratch zr{z.part, z.st};
+  // x0 may still be in flight on the plan's stream; the iteration runs on the
+  // state's own stream and the call returns after it has finished
+  if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
+  hipStream_t s = z.s;
   double h[3];
   // x = x0 / ||x0||_2 (x0 = all ones when absent)
   const double* src = x0;
   if (src == nullptr) {
-    hipLaunchKernelGGL(z_fill, dim3(vgrid(n)), dim3(kZBlock), 0, s, x, n, 1.0);
-    src = x;
+    hipLaunchKernelGGL(z_fill, dim3(vgrid(n)), dim3(kZBlock), 0, s, z.x, n, 1.0);
+    src = z.x;
   }
-  if (reduce3(src, src, n, 0.0, z, s, h) != hipSuccess) return STTSV_EHIP;
+  if (reduce3(src, src, n, 0.0, zr, s, h) != hipSuccess) return STTSV_EHIP;
   if (!(h[2] > 0.0) || !std::isfinite(h[2])) return STTSV_ENUMERIC;
-  hipLaunchKernelGGL(z_update, dim3(vgrid(n)), dim3(kZBlock), 0, s, x, src, n, 0.0, (const double*)z.st, 1);
-  // lambda_0
-  if (launch_sttsv(p, x, z.y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
-  if (reduce3(x, z.y, n, alpha, z, s, h) != hipSuccess) return STTSV_EHIP;
-  double lam = h[0];
-  int32_t it = 0;
-  bool conv = false;
-  while (it < max_iter) {
-    if (!(h[1] > 0.0) || !std::isfinite(h[1])) return STTSV_ENUMERIC;
-    hipLaunchKernelGGL(z_update, dim3(vgrid(n)), dim3(kZBlock), 0, s, x, (const double*)z.y, n, alpha,
-                       (const double*)z.st, 0);
-    if (launch_sttsv(p, x, z.y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
-    if (reduce3(x, z.y, n, alpha, z, s, h) != hipSuccess) return STTSV_EHIP;
-    ++it;
-    const bool done = tol > 0.0 && std::fabs(h[0] - lam) <= tol * std::fabs(h[0]);
-    lam = h[0];
-    if (done) {
-      conv = true;
-      break;
+  hipLaunchKernelGGL(z_update, dim3(vgrid(n)), dim3(kZBlock), 0, s, z.x, src, n, 0.0, (const double*)z.st, 1);
+  // lambda_0 and the control block
+  if (launch_sttsv(p, z.x, z.y, STTSV_PREC_FP64, nullptr, s) != hipSuccess) return STTSV_EHIP;
+  hipLaunchKernelGGL(z_stage, dim3(kZGrid), dim3(kZBlock), 0, s, (const double*)z.x, (const double*)z.y, n, alpha,
+                     z.part);
+  hipLaunchKernelGGL(z_final, dim3(1), dim3(kZBlock), 0, s, (const double*)z.part, z.st);
+  hipLaunchKernelGGL(z_ctrl_init, dim3(1), dim3(1), 0, s, (const double*)z.st, z.ctrl, alpha, tol, max_iter);
+  if (hipGetLastError() != hipSuccess) return STTSV_EHIP;
+  // updates: a captured graph of kZSteps updates (shift and tolerance live in
+  // the control block, so one graph serves every call on the plan), replayed
+  // until the control block says done
+  if (z.exec == nullptr) {
+    if (hipStreamSynchronize(s) != hipSuccess) return STTSV_EHIP;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return STTSV_EHIP;
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < kZSteps && e == hipSuccess; ++t) e = enqueue_update(p, z, s);
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return STTSV_EHIP;
+    }
+    e = hipGraphInstantiate(&z.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      z.exec = nullptr;
+      return STTSV_EHIP;
     }
   }
-  // residual ||B x^(r-1) - lambda x||_2 at the returned x
-  if (reduce3(x, z.y, n, -lam, z, s, h) != hipSuccess) return STTSV_EHIP;
+  for (;;) {
+    if (hipMemcpyAsync(z.hctrl, z.ctrl, sizeof(ZCtrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return STTSV_EHIP;
+    if (z.hctrl->done) break;
+    if (hipGraphLaunch(z.exec, s) != hipSuccess) return STTSV_EHIP;
+  }
+  const ZCtrl c = *z.hctrl;
+  if (c.status != STTSV_OK) return c.status;
+  // the result, and the residual ||B x^(r-1) - lambda x||_2 at it
+  if (hipMemcpyAsync(x, z.x, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return STTSV_EHIP;
+  if (reduce3(z.x, z.y, n, -c.lam, zr, s, h) != hipSuccess) return STTSV_EHIP;   // synchronises s
   if (info) {
-    info->iterations = it;
-    info->converged = conv ? 1 : 0;
-    info->lambda = lam;
+    info->iterations = c.iter;
+    info->converged = c.conv;
+    info->lambda = c.lam;
     info->residual = std::sqrt(h[1]);
   }
-  return conv ? STTSV_OK : STTSV_ENOTCONV;
+  return c.conv ? STTSV_OK : STTSV_ENOTCONV;
 }
 
 }  // namespace sttsv

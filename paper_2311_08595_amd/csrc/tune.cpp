@@ -223,7 +223,8 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
     }
   }
   if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
-  free_solver(p);                 // the captured launch sequence changes
+  free_solver(p);                 // the captured launch sequences change
+  free_zstate(p);
   int rc = STTSV_OK;
   for (Bucket& B : p.buckets)
     if (rc == STTSV_OK) rc = set_reuse(p, B, (p.flags & STTSV_FLAG_PREFIX_REUSE) != 0);

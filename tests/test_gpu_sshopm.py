@@ -152,3 +152,34 @@ def test_sshopm_errors(torch_cuda):
             plan.zeig_sshopm(z, alpha=1.0)          # zero start: ENUMERIC, nothing launched after the norm
         _, info = plan.zeig_sshopm(None, alpha=1.0, tol=0.0, max_iter=3, raise_on_notconv=False)
         assert info["status"] == _lib.STTSV_ENOTCONV and info["iterations"] == 3
+
+
+def test_sshopm_graph_reuse_across_calls_and_retune(torch_cuda):
+    """The K-update graph is captured once per plan with the shift and the
+    tolerance in the device control block: calls with other shifts, stopping
+    rules and start vectors on one plan, and a call after autotuning (which
+    drops the graph), give bit for bit what a fresh plan gives."""
+    import paper_2311_08595_amd as st
+    _say("[sshopm] graph reuse")
+    eptr, eidx, x0 = _mixed(11, 300, 1500, 6, 1, 6)
+    n, r = 300, 6
+    lam0 = sshopm_ref.contract(eptr, eidx, n, r, x0 / np.linalg.norm(x0))
+    calls = [(2.0 * lam0, 0.0, 5, True), (0.0, 0.0, 11, True), (lam0, 1e-12, 400, False), (3.0 * lam0, 0.0, 1, True)]
+
+    def run(plan, alpha, tol, k, from_x0):
+        x0d = torch_cuda.tensor(x0, dtype=torch_cuda.float64, device="cuda")
+        x, info = plan.zeig_sshopm(x0d if from_x0 else None, alpha=alpha, tol=tol, max_iter=k,
+                                   raise_on_notconv=False)
+        assert np.array_equal(x0d.cpu().numpy(), x0)          # the start vector is not written
+        return x.cpu().numpy().tobytes(), info["lambda_"], info["iterations"]
+
+    fresh = []
+    for c in calls:
+        with st.Plan(eptr, eidx, n, r) as plan:
+            fresh.append(run(plan, *c))
+    with st.Plan(eptr, eidx, n, r) as plan:
+        for c, want in zip(calls, fresh):
+            assert run(plan, *c) == want
+        plan.autotune(torch_cuda.tensor(x0, dtype=torch_cuda.float64, device="cuda"), reps=1)
+        for c, want in zip(calls, fresh):
+            assert run(plan, *c) == want

@@ -177,8 +177,10 @@ int sttsv_apply_naive(sttsv_plan_t plan, const double* x, double* y);
  *   x    device double[n]
  *   y    device double[n], receives B x^(r-1) (FP64 series, as sttsv_apply_prec)
  *   out  host double: B x^r, summed by a fixed-shape tree (reproducible bit for bit)
- * Synchronous on the plan's stream; allocates ~1.6k doubles of device scratch
- * for the call.  On a batched plan the contraction is over the disjoint union.
+ * Synchronous on the plan's stream; its reduction scratch lives in the plan
+ * (allocated on the first call of this or zeigvec_sshopm, 2 n + ~1.6k
+ * doubles, freed with the plan).  On a batched plan the contraction is over
+ * the disjoint union.
  * Errors: EINVAL (NULL argument, x == y), ENOMEM, EHIP.
  */
 int sttsv_contract(sttsv_plan_t plan, const double* x, double* y, double* out);
@@ -217,11 +219,17 @@ typedef struct {
  *   x_out     device double[n]: the last iterate (unit 2-norm)
  *   info      host, nullable
  * On a batched plan the tensor is that of the disjoint union of its graphs.
- * FP64 series whatever the plan's precision.  Synchronous; allocates its own
- * device scratch (2 n + ~1600 doubles) for the call.  Errors: EINVAL (NULL plan
- * or x_out, alpha < 0, tol < 0, max_iter < 0), ENUMERIC (zero or non-finite
- * norm), ENOTCONV (max_iter reached: x_out and info hold the last iterate),
- * ENOMEM, EHIP.
+ * FP64 series whatever the plan's precision.  Synchronous: waits for the
+ * plan's stream (x0 may be produced there), iterates on a stream of its own
+ * and returns when done.  lambda, the stopping test and the iteration count
+ * stay on the device; 8 updates are one captured graph, replayed until the
+ * device says stop, the host reading a small control block between replays.
+ * Scratch (2 n + ~1.6k doubles) and the graph live in the plan from the first
+ * call on (the graph is dropped when sttsv_plan_autotune changes the launch
+ * sequence).  Errors: EINVAL (NULL plan or x_out, alpha < 0, tol < 0,
+ * max_iter < 0), ENUMERIC (zero or non-finite norm; x_out untouched),
+ * ENOTCONV (max_iter reached: x_out and info hold the last iterate), ENOMEM,
+ * EHIP.
  */
 int zeigvec_sshopm(sttsv_plan_t plan, const double* x0, double alpha, double tol, int32_t max_iter,
                    double* x_out, sttsv_zeig_info* info);

@@ -44,12 +44,6 @@ def edge_fma(k, r):
     return 2 * (k - 3) * prod + (k + 1) * W - 1
 
 
-def edge_bytes(k):
-    """Algorithmic HBM bytes of one edge: member ids (4k), gathered x (8k),
-    contributions written (8k)."""
-    return 20 * k
-
-
 def stage_table(plan, xd, yd, prec, reps):
     from paper_2311_08595_amd import _lib
     lib = _lib.load()
@@ -74,14 +68,19 @@ GEN_LO = [1, 9, 17, 25, 33, 41, 49, 57]
 GEN_HI = [8, 16, 24, 32, 40, 48, 56, 63]
 
 
-def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None):
+def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64"):
     """Algorithmic FLOPs and HBM bytes of every stage.  Edge stages: series
     FMAs x 2 and 20 B per incidence (member id, gathered x, contribution);
     fused generic stages: the same summed over the buckets that no per-bucket
     stage covers and whose window is in the stage's range; the copy of x into
     degree-rank order: 4 B index + 8 B read + 8 B written per vertex;
     reduction levels: per term the value read (8 B, plus its 2 B LDS slot at
-    level 0), per chunk its 12 B descriptor and the 8 B result."""
+    level 0), per chunk its 12 B descriptor and the 8 B result.  An FP32
+    apply runs compact: 12 B per incidence (4 B id, FP32 x, 32-bit
+    contribution), 4 B more per vertex for the FP32 copy of x, and 4 B per
+    level-0 term read."""
+    compact = prec == "fp32"
+    inc_b = 12.0 if compact else 20.0
     per_bucket = {s["size"] for s in stages if s["kind"] == 0}
     if bucket_l is None:
         bucket_l = [0] * len(bucket_k)
@@ -89,7 +88,7 @@ def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None):
     for s in stages:
         if s["kind"] == 0:
             k, m = s["size"], s["count"]
-            out.append((2.0 * edge_fma(k, r) * m, edge_bytes(k) * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m)))
+            out.append((2.0 * edge_fma(k, r) * m, inc_b * k * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m)))
         elif s["kind"] in (1, 4):
             g = s["size"]
             f = b = 0.0
@@ -98,13 +97,13 @@ def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None):
                 if (k >= 4 and k not in per_bucket and GEN_LO[g] <= W <= GEN_HI[g]
                         and (lanes > 0) == (s["kind"] == 4)):
                     f += 2.0 * edge_fma(k, r) * m
-                    b += edge_bytes(k) * m
+                    b += inc_b * k * m
             what = "generic" if s["kind"] == 1 else "lane-group"
             out.append((f, b, "%s edges W in [%d,%d], %d edges" % (what, GEN_LO[g], GEN_HI[g], s["count"])))
         elif s["kind"] == 3:
-            out.append((0.0, 20.0 * s["count"], "x into degree-rank order, n=%d" % s["count"]))
+            out.append((0.0, (24.0 if compact else 20.0) * s["count"], "x into degree-rank order, n=%d" % s["count"]))
         else:
-            per_term = 10.0 if s["size"] == 0 else 8.0
+            per_term = (6.0 if compact else 10.0) if s["size"] == 0 else 8.0
             out.append((0.0, per_term * s["in_len"] + 20.0 * s["count"],
                         "reduce level %d, %d chunks" % (s["size"], s["count"])))
     return out
@@ -328,7 +327,7 @@ def _stage_rooflines(plan, xd, yd, r, nnz, reps, workload=None):
             if st_["kind"] == 2:
                 st_["in_len"] = prev
                 prev = st_["count"]
-        work = stage_work(stages, bk, bm, r, bl)
+        work = stage_work(stages, bk, bm, r, bl, prec)
         best, roof = roofline_of(stages, work, prec, r, workload)
         roof["avg_kernel_ms"] = best["ms"]
         roof["stages_ms_sum"] = sum(s_["ms"] for s_ in stages)
@@ -486,7 +485,7 @@ def profile_apply(a):
                 if st_["kind"] == 2:
                     st_["in_len"] = prev
                     prev = st_["count"]
-            work = stage_work(stages, bk, bm, w["r"], bl)
+            work = stage_work(stages, bk, bm, w["r"], bl, prec)
             i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
             kname, grid = stage_kernel(stages[i], prec, w["r"])
             log("[profile] %s %s: %d applies, %d stage-timed passes; dominant stage %s (kernel %s, grid %s): "
@@ -844,7 +843,7 @@ def main():
     from paper_2311_08595_amd import _lib
     bk, bm = res["bucket_k"], res["bucket_m"]
     for prec in ("fp64", "fp32"):
-        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r, res["bucket_l"])
+        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r, res["bucket_l"], prec)
     best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64", r, "zipf")
     roof["avg_kernel_ms"] = best["ms"]
     out["roofline"] = roof

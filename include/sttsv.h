@@ -49,7 +49,12 @@ extern "C" {
 /* ---- precision of the series arithmetic ------------------------------- */
 #define STTSV_PREC_FP64       0  /* series, weights, sums all in FP64               */
 #define STTSV_PREC_FP32       1  /* series in FP32 (FMA), weights / products /      */
-                                 /* per-vertex sums in FP64                         */
+                                 /* per-vertex sums in FP64; an apply gathers x    */
+                                 /* rounded to FP32 and stores each contribution   */
+                                 /* as the upper 32 bits of its FP64 value (FP64   */
+                                 /* range, 21 significant bits, rounded to nearest)*/
+                                 /* which the reduction widens back exactly.  The  */
+                                 /* solver's FP32 phase keeps FP64 x and terms.    */
 
 typedef struct sttsv_plan_s* sttsv_plan_t;
 
@@ -541,7 +546,9 @@ int sym_cp_descent(sttsv_plan_t plan, int32_t R, double* A, double* lambda, int3
 #define STTSV_Q_BUCKET_R    8  /* int64[nb]  tensor order of each bucket          */
 #define STTSV_Q_CONTRIB    10  /* double[nnz] the per-incidence contributions of  */
                                /*            the last apply, in node-major order  */
-                               /*            (synchronises the plan's stream)      */
+                               /*            (an FP32 apply stores them as 32-bit */
+                               /*            words: widened back exactly here;    */
+                               /*            synchronises the plan's stream)      */
 #define STTSV_Q_BUCKET_LANES 11 /* int64[nb] lanes per edge of each bucket's FP64 */
                                /*            kernel (0: one lane per edge; else a  */
                                /*            lane group, see sttsv_apply_timed)    */

@@ -22,6 +22,8 @@ ARCH = os.environ.get("STTSV_ARCH", "gfx950")
 
 HIP_SOURCES = (["edge_part%d.hip" % i for i in range(8)] + ["edge_gen%d.hip" % i for i in range(8)]
                + ["edge_coop%d.hip" % i for i in range(4)]
+               + ["edge_cpart%d.hip" % i for i in range(8)] + ["edge_cgen%d.hip" % i for i in range(2)]
+               + ["edge_ccoop%d.hip" % i for i in range(2)]
                + ["apply.hip", "reduce.hip", "nqz.hip", "mpnn.hip", "naive.hip", "sshopm.hip", "ccss.hip", "cp.hip"])
 CXX_SOURCES = ["plan.cpp", "api.cpp", "tune.cpp"]
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off"]

@@ -30,6 +30,18 @@ void fill_edge_coop0(EdgeTables&);
 void fill_edge_coop1(EdgeTables&);
 void fill_edge_coop2(EdgeTables&);
 void fill_edge_coop3(EdgeTables&);
+void fill_edge_cpart0(EdgeTables&);
+void fill_edge_cpart1(EdgeTables&);
+void fill_edge_cpart2(EdgeTables&);
+void fill_edge_cpart3(EdgeTables&);
+void fill_edge_cpart4(EdgeTables&);
+void fill_edge_cpart5(EdgeTables&);
+void fill_edge_cpart6(EdgeTables&);
+void fill_edge_cpart7(EdgeTables&);
+void fill_edge_cgen0(EdgeTables&);
+void fill_edge_cgen1(EdgeTables&);
+void fill_edge_ccoop0(EdgeTables&);
+void fill_edge_ccoop1(EdgeTables&);
 
 namespace {
 
@@ -47,15 +59,20 @@ __global__ void __launch_bounds__(256) edge_k1(EdgeCall c, BucketDesc b) {
   double p = 1.0;
   for (int j = 0; j < b.r - 1; ++j) p *= f;
   if (b.wgt != nullptr) p *= b.wgt[i] / b.wk;
-  c.contrib[b.loc[i]] = ldexp(p, (b.r - 1) * e2);
+  store_contrib(c, b.loc[i], ldexp(p, (b.r - 1) * e2));
 }
 
-// x into degree-rank order: xr[p] = x[rid[p]].
+// x into degree-rank order: xr[p] = x[rid[p]] (and rounded to FP32 into
+// xr32 when it is not null).
 __global__ void __launch_bounds__(256) permute_x(const double* __restrict__ x, const int32_t* __restrict__ rid,
-                                                 int64_t n, double* __restrict__ xr, const int32_t* done) {
+                                                 int64_t n, double* __restrict__ xr, float* __restrict__ xr32,
+                                                 const int32_t* done) {
   if (done != nullptr && *done) return;
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p < n) xr[p] = x[rid[p]];
+  if (p >= n) return;
+  const double v = x[rid[p]];
+  xr[p] = v;
+  if (xr32 != nullptr) xr32[p] = static_cast<float>(v);
 }
 
 hipError_t launch_k1(const EdgeCall& c, const BucketDesc& b, hipStream_t s) {
@@ -86,6 +103,18 @@ EdgeTables build_tables() {
   fill_edge_coop1(t);
   fill_edge_coop2(t);
   fill_edge_coop3(t);
+  fill_edge_cpart0(t);
+  fill_edge_cpart1(t);
+  fill_edge_cpart2(t);
+  fill_edge_cpart3(t);
+  fill_edge_cpart4(t);
+  fill_edge_cpart5(t);
+  fill_edge_cpart6(t);
+  fill_edge_cpart7(t);
+  fill_edge_cgen0(t);
+  fill_edge_cgen1(t);
+  fill_edge_ccoop0(t);
+  fill_edge_ccoop1(t);
   t.k1 = &launch_k1;
   return t;
 }
@@ -183,6 +212,14 @@ void build_stages(Plan& p) {
       if (p.groups[g].seq == seq) st.push_back(Stage{1, static_cast<int>(g), p.groups[g].f64});
     for (size_t l = 0; l < p.levels.size(); ++l) st.push_back(Stage{2, static_cast<int>(l), true});
   }
+  // FP32 applies run compact unless an edge stage of size >= 2 falls back to
+  // FP64 series (its kernels store FP64 contributions); size-1 edges store
+  // either form
+  p.compact_ok = true;
+  for (const Stage& S : p.stages[1]) {
+    if (S.type == 0 && S.f64 && p.buckets[S.index].k != 1) p.compact_ok = false;
+    if (S.type == 1 && S.f64) p.compact_ok = false;
+  }
   assign_lanes(p);
 }
 
@@ -190,19 +227,28 @@ int stage_count(const Plan& p, int precision) {
   return static_cast<int>(p.stages[precision == STTSV_PREC_FP32 ? 1 : 0].size());
 }
 
-static hipError_t launch_permute(Plan& p, const double* x, const int32_t* done, hipStream_t s) {
+static hipError_t launch_permute(Plan& p, const double* x, const int32_t* done, hipStream_t s, bool compact) {
   if (p.n == 0) return hipSuccess;
   hipLaunchKernelGGL(permute_x, dim3(static_cast<unsigned>((p.n + 255) / 256)), dim3(256), 0, s, x,
-                     (const int32_t*)p.d_rid, (int64_t)p.n, p.d_xr, done);
+                     (const int32_t*)p.d_rid, (int64_t)p.n, p.d_xr, compact ? p.d_xr32 : nullptr, done);
   return hipGetLastError();
 }
 
-hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s) { return launch_permute(p, x, nullptr, s); }
+hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s) {
+  return launch_permute(p, x, nullptr, s, false);
+}
+
+// The edge-launch arguments of one apply: compact (FP32 apply) or not.
+static EdgeCall edge_call(Plan& p, const double* xr, const int32_t* done, const int32_t* gskip, bool compact) {
+  return EdgeCall{xr, p.d_contrib, done, gskip, compact ? p.d_xr32 : nullptr,
+                  compact ? reinterpret_cast<uint32_t*>(p.d_contrib) : nullptr};
+}
 
 // c.x: the caller's x for the permute stage, the rank-ordered copy for edge stages
 static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, double* y, hipStream_t s) {
   const EdgeTables& tab = edge_tables();
-  if (S.type == 3) return launch_permute(p, c.x, c.done, s);
+  const bool compact = c.contrib32 != nullptr;
+  if (S.type == 3) return launch_permute(p, c.x, c.done, s, compact);
   if (S.type == 0) {
     const Bucket& B = p.buckets[S.index];
     const BucketDesc& d = B.desc[S.f64 ? 0 : 1];
@@ -211,31 +257,37 @@ static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, 
       const SmallLaunchFn fr = tab.run64[B.k - 4][d.W];
       return fr ? fr(c, d, s) : hipErrorInvalidValue;
     }
-    const SmallLaunchFn fn = S.f64 ? tab.small64[B.small_kind[0]][d.W] : tab.small32[B.small_kind[1]][d.W];
+    if (compact && S.f64) return hipErrorInvalidValue;     // the plan's compact_ok rules this out
+    const SmallLaunchFn fn = S.f64 ? tab.small64[B.small_kind[0]][d.W]
+                                   : (compact ? tab.small32c : tab.small32)[B.small_kind[1]][d.W];
     return fn ? fn(c, d, s) : hipErrorInvalidValue;
   }
   if (S.type == 1) {
     const GenGroup& G = p.groups[S.index];
-    const GenLaunchFn fn = G.coop ? (G.f64 ? tab.coop64[G.range] : tab.coop32[G.range])
-                                  : (G.f64 ? tab.gen64[G.range] : tab.gen32[G.range]);
+    if (compact && G.f64) return hipErrorInvalidValue;
+    const GenLaunchFn fn = G.coop ? (G.f64 ? tab.coop64[G.range] : (compact ? tab.coop32c : tab.coop32)[G.range])
+                                  : (G.f64 ? tab.gen64[G.range] : (compact ? tab.gen32c : tab.gen32)[G.range]);
     return fn ? fn(c, G.d_bks, G.d_tasks, G.ntasks, G.lds, s) : hipErrorInvalidValue;
   }
   const size_t l = static_cast<size_t>(S.index);
-  const double* in = l == 0 ? p.d_contrib : p.d_partials[l - 1];
+  const void* in = l == 0 ? static_cast<const void*>(p.d_contrib) : p.d_partials[l - 1];
   double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
-  return launch_reduce_level(p.levels[l], in, y, next, c.done, s);
+  return launch_reduce_level(p.levels[l], in, y, next, c.done, s, false, compact && l == 0);
 }
 
 hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s) {
   const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
-  return launch_stage_call(p, S, EdgeCall{S.type == 3 ? x : p.d_xr, p.d_contrib, done, nullptr}, y, s);
+  const bool compact = precision == STTSV_PREC_FP32 && p.compact_ok;
+  if (S.type != 2) p.contrib_compact = compact;
+  return launch_stage_call(p, S, edge_call(p, S.type == 3 ? x : p.d_xr, done, nullptr, compact), y, s);
 }
 
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s) {
-  const hipError_t e = launch_edges(p, x, precision, done, nullptr, s);
-  return e != hipSuccess ? e : launch_reduction(p, y, done, s);
+  const bool compact = precision == STTSV_PREC_FP32 && p.compact_ok;
+  const hipError_t e = launch_edges(p, x, precision, done, nullptr, s, XOrder::kVertex, compact);
+  return e != hipSuccess ? e : launch_reduction(p, y, done, s, false, compact);
 }
 
 int init_lanes(Plan& p) {
@@ -250,13 +302,13 @@ int init_lanes(Plan& p) {
 // Edge stages of np precisions (precs[i] with per-graph skip flags skips[i])
 // inside one fork/join of the stream lanes.
 static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, const int32_t* const* skips, int np,
-                                   const int32_t* done, hipStream_t s, XOrder order) {
+                                   const int32_t* done, hipStream_t s, XOrder order, bool compact) {
   const double* xr = order == XOrder::kRank ? x : p.d_xr;
   const bool multi = !(p.flags & STTSV_FLAG_ONE_STREAM) && p.ev_fork != nullptr;
   int nl = 1;
   if (multi)
     for (int i = 0; i < np; ++i) nl = std::max(nl, p.lanes[precs[i] == STTSV_PREC_FP32 ? 1 : 0]);
-  hipError_t e = order == XOrder::kVertex ? launch_permute(p, x, done, s) : hipSuccess;
+  hipError_t e = order == XOrder::kVertex ? launch_permute(p, x, done, s, compact) : hipSuccess;
   if (e != hipSuccess) return e;
   if (nl > 1) {
     // fork: every helper lane starts after the work already on s
@@ -267,7 +319,7 @@ static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, c
   for (int i = 0; i < np && e == hipSuccess; ++i) {
     const int seq = precs[i] == STTSV_PREC_FP32 ? 1 : 0;
     const bool lanes = nl > 1 && p.lanes[seq] > 1;
-    const EdgeCall c{xr, p.d_contrib, done, skips[i]};
+    const EdgeCall c = edge_call(p, xr, done, skips[i], compact);
     for (const Stage& S : p.stages[seq]) {
       if (S.type == 2 || S.type == 3) continue;
       const hipStream_t ls = lanes && S.lane > 0 ? p.aux[S.lane - 1] : s;
@@ -290,22 +342,27 @@ static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, c
 }
 
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s, XOrder order) {
-  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order);
+                        hipStream_t s, XOrder order, bool compact) {
+  // a compact launch needs the FP32 copy of x, which only the permute makes
+  if (compact && (precision != STTSV_PREC_FP32 || order != XOrder::kVertex || !p.compact_ok))
+    return hipErrorInvalidValue;
+  p.contrib_compact = compact;
+  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order, compact);
 }
 
 hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
                              const int32_t* skip64, hipStream_t s) {
   const int precs[2] = {STTSV_PREC_FP32, STTSV_PREC_FP64};
   const int32_t* skips[2] = {skip32, skip64};
-  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank);
+  p.contrib_compact = false;
+  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank, false);
 }
 
-hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out) {
+hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out, bool compact) {
   for (size_t l = 0; l < p.levels.size(); ++l) {
-    const double* in = l == 0 ? p.d_contrib : p.d_partials[l - 1];
+    const void* in = l == 0 ? static_cast<const void*>(p.d_contrib) : p.d_partials[l - 1];
     double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
-    const hipError_t e = launch_reduce_level(p.levels[l], in, y, next, done, s, rank_out);
+    const hipError_t e = launch_reduce_level(p.levels[l], in, y, next, done, s, rank_out, compact && l == 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

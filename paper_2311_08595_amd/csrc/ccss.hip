@@ -435,6 +435,7 @@ hipError_t launch_ccss(Plan& p, const double* x, double* y, hipStream_t s) {
   hipError_t e = launch_permute_x(p, x, s);
   if (e != hipSuccess) return e;
   const EdgeCall c{p.d_xr, p.d_contrib, nullptr, nullptr};
+  p.contrib_compact = false;                     // FP64 contributions
   // size-1 edges: their own kernel (no path)
   for (const Bucket& B : p.buckets)
     if (B.k == 1 && (e = edge_tables().k1(c, B.desc[0], s)) != hipSuccess) return e;

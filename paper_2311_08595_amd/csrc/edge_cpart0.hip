@@ -1,0 +1,8 @@
+// Instantiates the compact FP32-apply variants (FP32 x, 32-bit
+// contributions) of the per-bucket edge kernels for series windows
+// W = 1..31.
+#include "edge_kernels.inc"
+
+namespace sttsv {
+void fill_edge_cpart0(EdgeTables& t) { fill_range<float, 1, 31, true>(t.small32c); }
+}  // namespace sttsv

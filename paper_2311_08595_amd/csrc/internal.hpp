@@ -64,7 +64,31 @@ struct EdgeCall {
   double* contrib;      // per-incidence contributions (one region per vertex block)
   const int32_t* done;  // whole launch is skipped when *done != 0 (nullable)
   const int32_t* gskip; // per-graph skip flags indexed by BucketDesc::gid (nullable)
+  // compact FP32 apply (both null otherwise): FP32-series kernels gather x
+  // from x32, and every kernel stores its contribution as the upper 32 bits
+  // of the FP64 value, rounded (contrib32 aliases contrib)
+  const float* x32;
+  uint32_t* contrib32;
 };
+
+#if defined(__HIP__)
+// A contribution as a compact FP32 apply stores it: the upper 32 bits of the
+// FP64 value rounded to nearest (ties away from zero), i.e. FP64's sign and
+// exponent range with 21 significant bits; the reduction widens it back
+// exactly.
+__device__ __forceinline__ uint32_t contrib_word(double v) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(__double_as_longlong(v)) + 0x80000000ull) >> 32);
+}
+
+// Store at place q in the call's format (run-time choice: for the size-1
+// kernel only; the series kernels choose at compile time).
+__device__ __forceinline__ void store_contrib(const EdgeCall& c, int64_t q, double v) {
+  if (c.contrib32 != nullptr)
+    c.contrib32[q] = contrib_word(v);
+  else
+    c.contrib[q] = v;
+}
+#endif
 
 // Plan-time description of one size bucket (device pointers offset to the
 // bucket's slot range).
@@ -102,11 +126,14 @@ using GenLaunchFn = hipError_t (*)(const EdgeCall&, const BucketDesc* bks, const
 struct EdgeTables {
   SmallLaunchFn small64[SK_COUNT][kMaxW + 1];
   SmallLaunchFn small32[SK_COUNT][kMaxW + 1];
+  SmallLaunchFn small32c[SK_COUNT][kMaxW + 1];   // compact FP32-apply variants (FP32 x, 32-bit contributions)
   SmallLaunchFn run64[4][kMaxW + 1];     // prefix-reuse variants, k = 4..7, FP64
   GenLaunchFn gen64[kGenRanges];
   GenLaunchFn gen32[kGenRanges];
+  GenLaunchFn gen32c[kGenRanges];
   GenLaunchFn coop64[kGenRanges];        // fused lane-group kernels by window range (FP64, FP32 series)
   GenLaunchFn coop32[kGenRanges];
+  GenLaunchFn coop32c[kGenRanges];
   SmallLaunchFn k1;
 };
 
@@ -228,6 +255,7 @@ struct Plan {
   int32_t* d_mem = nullptr;       // member slots as degree-rank positions (what the kernels gather by)
   int32_t* d_rid = nullptr;       // vertex id at every degree-rank position
   double* d_xr = nullptr;         // x in degree-rank order (written by the permute stage)
+  float* d_xr32 = nullptr;        // ... and rounded to FP32 (compact FP32 applies)
   std::vector<int32_t> vblock;    // vertex block of every vertex
   std::vector<int64_t> region;    // first contribution index of every block (+ nnz at the end)
   int32_t* d_loc = nullptr;       // contribution index of every member slot
@@ -242,6 +270,8 @@ struct Plan {
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
   double* d_wgt = nullptr;        // per canonical edge w(e)/|beta(e)| (r-1)! (edge-weighted plans only)
   double* d_contrib = nullptr;    // contributions, one region per vertex block
+  bool contrib_compact = false;   // the last apply stored 32-bit contributions (FP32 apply)
+  bool compact_ok = false;        // every FP32-list edge stage (k >= 2) runs FP32 series: FP32 applies run compact
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
   std::vector<Stage> stages[2];   // launch sequence per precision [fp64, fp32]
   int lanes[2] = {1, 1};          // stream lanes the edge stages use, per precision
@@ -272,6 +302,8 @@ void free_plan(Plan* p);
 
 // STTSV launch sequence (apply.hip): per-bucket edge kernels and fused
 // generic groups, then one stage per reduction level.
+// An FP32 apply (precision STTSV_PREC_FP32) runs compact: FP32 copy of x,
+// 32-bit contributions and a level-0 reduction that reads them.
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
                         const int32_t* done, hipStream_t s);
 int stage_count(const Plan& p, int precision);
@@ -291,14 +323,15 @@ int set_reuse(Plan& p, Bucket& b, bool by_flag);   // prefix-reuse runs of a buc
 // order first), already in rank order, or copied by an earlier launch.
 enum class XOrder { kVertex, kRank, kCopied };
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s, XOrder order = XOrder::kVertex);
+                        hipStream_t s, XOrder order = XOrder::kVertex, bool compact = false);
 // rank_out: write y in degree-rank order instead of vertex order.
 // FP32- and FP64-series edge stages (x already in rank order) inside one
 // fork/join, each gated by its own per-graph skip flags: the solver's mixed
 // schedule, where each graph runs one of the two per iteration.
 hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
                              const int32_t* skip64, hipStream_t s);
-hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false);
+hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false,
+                            bool compact = false);
 
 // x into degree-rank order (the copy the edge kernels gather from)
 hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s);
@@ -316,8 +349,8 @@ int cp_objective_grad(Plan& p, int32_t R, const double* A, const double* lambda,
 int cp_descent(Plan& p, int32_t R, double* A, double* lambda, int32_t iters, double step, sttsv_cp_info* info);
 
 // reduction kernels (reduce.hip)
-hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
-                               const int32_t* done, hipStream_t s, bool rank_out = false);
+hipError_t launch_reduce_level(const ReduceLevel& L, const void* in, double* y, double* next,
+                               const int32_t* done, hipStream_t s, bool rank_out = false, bool compact = false);
 
 // autotuner (tune.cpp)
 int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t* tuned);

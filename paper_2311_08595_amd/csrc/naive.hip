@@ -113,6 +113,7 @@ hipError_t launch_sttsv_naive(Plan& p, const double* x, double* y, hipStream_t s
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const EdgeCall c{p.d_xr, p.d_contrib, nullptr, nullptr};
+  p.contrib_compact = false;                     // FP64 contributions
   for (const Bucket& B : p.buckets)
     if ((e = launch_naive_bucket(c, B.desc[0], s)) != hipSuccess) return e;
   return launch_reduction(p, y, nullptr, s);

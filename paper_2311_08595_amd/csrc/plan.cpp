@@ -278,6 +278,7 @@ void free_plan(Plan* p) {
   (void)hipFree(p->d_mem);
   (void)hipFree(p->d_rid);
   (void)hipFree(p->d_xr);
+  (void)hipFree(p->d_xr32);
   (void)hipFree(p->d_loc);
   (void)hipFree(p->d_gid);
   (void)hipFree(p->d_wgt);
@@ -925,6 +926,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   std::vector<int32_t> rpos(n);   // degree-rank position of every vertex
   for (int32_t q = 0; q < n; ++q) rpos[rid[q]] = q;
   if ((rc = upload<double>(&P->d_xr, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload<float>(&P->d_xr32, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);

@@ -43,10 +43,15 @@ __device__ __forceinline__ double lane_down(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// A term as stored: FP64, or (compact FP32 applies) the upper 32 bits of the
+// FP64 value, which widen back exactly.
+__device__ __forceinline__ double term(double v) { return v; }
+__device__ __forceinline__ double term(uint32_t w) { return __hiloint2double(static_cast<int>(w), 0); }
+
 // Levels >= 1: chunk c of the level is summed by lanes 8c .. 8c+7.
-template <bool RANK>
+template <bool RANK, typename In>
 __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ desc, int64_t nchunks,
-                                                    const double* __restrict__ in,
+                                                    const In* __restrict__ in,
                                                     double* __restrict__ y, double* __restrict__ next,
                                                     const int32_t* done) {
   if (done != nullptr && *done) return;     // uniform: every lane leaves together
@@ -60,7 +65,7 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
 #pragma unroll
   for (int q = 0; q < kPerLane; ++q) {   // all loads first; an absent term re-reads the chunk's first
     const int p = j + q * kGroup;
-    t[q] = in[p < l ? s + p : s];
+    t[q] = term(in[p < l ? s + p : s]);
   }
   double v = 0.0;
 #pragma unroll
@@ -79,20 +84,22 @@ __global__ void __launch_bounds__(256) reduce_level(const int4* __restrict__ des
 
 // Copy src[0 .. len) into LDS, term i to st[pos[i]], kCopyDepth loads in
 // flight per thread.
-__device__ __forceinline__ void stage_range(const double* __restrict__ src, const uint16_t* __restrict__ pos,
+template <typename In>
+__device__ __forceinline__ void stage_range(const In* __restrict__ src, const uint16_t* __restrict__ pos,
                                             double* st, int len) {
   for (int i0 = 0; i0 < len; i0 += kStageThreads * kCopyDepth) {
-    double t[kCopyDepth];
+    In t[kCopyDepth];
     int k[kCopyDepth];
 #pragma unroll
-    for (int u = 0; u < kCopyDepth; ++u) {
+    for (int u = 0; u < kCopyDepth; ++u) {   // unconditional loads (index clamped): all in flight at once
       const int i = i0 + u * kStageThreads + static_cast<int>(threadIdx.x);
-      t[u] = i < len ? src[i] : 0.0;
-      k[u] = i < len ? static_cast<int>(pos[i]) : -1;
+      const int ic = i < len ? i : len - 1;
+      t[u] = src[ic];
+      k[u] = i < len ? static_cast<int>(pos[ic]) : -1;
     }
 #pragma unroll
     for (int u = 0; u < kCopyDepth; ++u)
-      if (k[u] >= 0) st[k[u]] = t[u];
+      if (k[u] >= 0) st[k[u]] = term(t[u]);
   }
 }
 
@@ -151,11 +158,12 @@ __device__ __forceinline__ void stage_pass(int G, int2 d, const double* st, doub
   }
 }
 
+template <typename In>
 __global__ void __launch_bounds__(kStageThreads) reduce_level0(const int2* __restrict__ desc,
                                                                const int4* __restrict__ wg,
                                                                const int2* __restrict__ ranges,
                                                                const uint16_t* __restrict__ lpos,
-                                                               const double* __restrict__ in,
+                                                               const In* __restrict__ in,
                                                                double* __restrict__ y, double* __restrict__ next,
                                                                const int32_t* done) {
   if (done != nullptr && *done) return;
@@ -183,21 +191,28 @@ __global__ void __launch_bounds__(kStageThreads) reduce_level0(const int2* __res
 
 }  // namespace
 
-hipError_t launch_reduce_level(const ReduceLevel& L, const double* in, double* y, double* next,
-                               const int32_t* done, hipStream_t s, bool rank_out) {
-  if (L.nchunks == 0) return hipSuccess;
+template <typename In>
+hipError_t launch_level(const ReduceLevel& L, const In* in, double* y, double* next, const int32_t* done,
+                        hipStream_t s, bool rank_out) {
   if (L.d_wg != nullptr) {
-    hipLaunchKernelGGL(reduce_level0, dim3(static_cast<unsigned>(L.nwg)), dim3(kStageThreads), 0, s,
+    hipLaunchKernelGGL((reduce_level0<In>), dim3(static_cast<unsigned>(L.nwg)), dim3(kStageThreads), 0, s,
                        L.d_desc0[rank_out ? 1 : 0], L.d_wg, L.d_ranges, L.d_lpos, in, y, next, done);
     return hipGetLastError();
   }
   const int64_t threads = L.nchunks * kGroup;
   const dim3 grid(static_cast<unsigned>((threads + 255) / 256));
   if (rank_out)
-    hipLaunchKernelGGL((reduce_level<true>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
+    hipLaunchKernelGGL((reduce_level<true, In>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
   else
-    hipLaunchKernelGGL((reduce_level<false>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
+    hipLaunchKernelGGL((reduce_level<false, In>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
   return hipGetLastError();
+}
+
+hipError_t launch_reduce_level(const ReduceLevel& L, const void* in, double* y, double* next,
+                               const int32_t* done, hipStream_t s, bool rank_out, bool compact) {
+  if (L.nchunks == 0) return hipSuccess;
+  return compact ? launch_level(L, static_cast<const uint32_t*>(in), y, next, done, s, rank_out)
+                 : launch_level(L, static_cast<const double*>(in), y, next, done, s, rank_out);
 }
 
 }  // namespace sttsv

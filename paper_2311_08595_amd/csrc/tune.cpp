@@ -105,7 +105,8 @@ float time_generic(Plan& p, Bucket& B, int t, bool lds, const EdgeCall& c, int r
       hipMalloc(&d_t, sizeof(GenTask) * tasks.size()) == hipSuccess &&
       hipMemcpy(d_b, &d, sizeof(BucketDesc), hipMemcpyHostToDevice) == hipSuccess &&
       hipMemcpy(d_t, tasks.data(), sizeof(GenTask) * tasks.size(), hipMemcpyHostToDevice) == hipSuccess) {
-    const GenLaunchFn fn = t == 0 ? tab.gen64[gen_range_of(W)] : tab.gen32[gen_range_of(W)];
+    const GenLaunchFn fn = t == 0 ? tab.gen64[gen_range_of(W)]
+                                  : (c.contrib32 != nullptr ? tab.gen32c : tab.gen32)[gen_range_of(W)];
     const size_t ldsb = lds ? static_cast<size_t>(need) : 0;
     if (fn != nullptr)
       ms = time_median([&] { return fn(c, d_b, d_t, (int64_t)tasks.size(), ldsb, p.stream); }, reps, p.stream);
@@ -162,9 +163,15 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
   if (x == nullptr || reps < 1) return STTSV_EINVAL;
   load_cache(cache_path);
   const EdgeTables& tab = edge_tables();
-  // the edge kernels gather from the rank-ordered copy of x: the first stage makes it
-  if (launch_stage(p, 0, x, nullptr, STTSV_PREC_FP64, nullptr, p.stream) != hipSuccess) return STTSV_EHIP;
-  const EdgeCall c{p.d_xr, p.d_contrib, nullptr, nullptr};
+  // the edge kernels gather from the rank-ordered copies of x: the first
+  // stage of an FP32 apply makes both (FP64 and FP32, when the plan's FP32
+  // applies run compact); FP32-series kernels are timed as an FP32 apply
+  // runs them
+  if (launch_stage(p, 0, x, nullptr, STTSV_PREC_FP32, nullptr, p.stream) != hipSuccess) return STTSV_EHIP;
+  const EdgeCall c64{p.d_xr, p.d_contrib, nullptr, nullptr, nullptr, nullptr};
+  const EdgeCall c32 = p.compact_ok ? EdgeCall{p.d_xr, p.d_contrib, nullptr, nullptr, p.d_xr32,
+                                               reinterpret_cast<uint32_t*>(p.d_contrib)}
+                                    : c64;
   int count = 0;
   for (Bucket& B : p.buckets) {
     if (B.k < 4) continue;
@@ -183,7 +190,8 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
           cached = true;
         }
       }
-      const auto& small = t == 0 ? tab.small64 : tab.small32;
+      const EdgeCall& c = t == 0 ? c64 : c32;
+      const auto& small = t == 0 ? tab.small64 : (c.contrib32 != nullptr ? tab.small32c : tab.small32);
       const SmallLaunchFn kr = (B.k <= 7 && !(p.flags & STTSV_FLAG_GENERIC_ONLY)) ? small[SK_R4 + (B.k - 4)][W] : nullptr;
       if (!cached) {
         const float g_lds = time_generic(p, B, t, true, c, reps);

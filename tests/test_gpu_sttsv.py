@@ -374,3 +374,25 @@ def test_autotune_keeps_bits(tmp_path):
             again = plan2.apply(xd, precision=prec).cpu().numpy()
         assert again.tobytes() == before.tobytes()
         assert len(open(cache).read().split()) > 0
+
+
+def test_compact_fp32_contributions_are_words(torch_cuda):
+    """An FP32 apply stores every contribution as the upper 32 bits of its
+    FP64 value, rounded to nearest: the contributions read back have zero low
+    words, and each lies within the 21-bit rounding (plus the FP32 series
+    error) of the FP64 apply's contribution at the same incidence."""
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    eptr, eidx, x = _mixed(41, 1500, 9000, 12, 1, 12)
+    with st.Plan(eptr, eidx, 1500, 12) as plan:
+        xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+        plan.apply(xd, precision="fp64")
+        c64 = plan.query(_lib.Q_CONTRIB)
+        plan.apply(xd, precision="fp32")
+        c32 = plan.query(_lib.Q_CONTRIB)
+    bits = c32.view(np.uint64)
+    assert np.all((bits & np.uint64(0xFFFFFFFF)) == 0)
+    nz = c64 != 0
+    assert np.max(np.abs(c32[nz] - c64[nz]) / np.abs(c64[nz])) <= 1e-5
+    assert not np.array_equal(c32, c64)

@@ -40,6 +40,8 @@ struct SCtrl {            // per solve
   int32_t all_done;
   int32_t max_iter;
   double tol, switch_tol, shift;
+  int32_t no32;          // no open graph runs FP32 series again (a graph never switches back)
+  int32_t pad;
 };
 
 struct Solver {
@@ -63,8 +65,10 @@ struct Solver {
   GCtrl* hctrl = nullptr;     // pinned host mirrors
   SCtrl* hsctrl = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec64 = nullptr;   // FP64-only iterations: the FP32->FP64 schedule once no32
   int graph_iters = 0;
   int graph_sched = -1;
+  int graph64_iters = 0;
 };
 
 namespace {
@@ -246,7 +250,10 @@ __global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
     c.done = 1;
     c.status = STTSV_ENUMERIC;
     S.skip64[g] = S.skip32[g] = 1;
-    if (S.G == 1) S.sctrl->all_done = 1;   // one graph: no separate all-done pass
+    if (S.G == 1) {                         // one graph: no separate all-done pass
+      S.sctrl->all_done = 1;
+      S.sctrl->no32 = 1;
+    }
     return;
   }
   c.inv_wmax = 1.0 / wm;
@@ -276,16 +283,26 @@ __global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
     c.status = STTSV_ENOTCONV;
   }
   if (c.done) S.skip64[g] = S.skip32[g] = 1;
-  if (S.G == 1) S.sctrl->all_done = c.done;
+  if (S.G == 1) {
+    S.sctrl->all_done = c.done;
+    S.sctrl->no32 = S.skip32[g];
+  }
 }
 
 // all_done = every graph done (single block)
 __global__ void __launch_bounds__(kRedBlock) all_done_check(Solver S) {
   __shared__ double sh[kRedBlock];
-  double open = 0.0;
-  for (int g = threadIdx.x; g < S.G; g += kRedBlock) open = fmax(open, S.ctrl[g].done ? 0.0 : 1.0);
+  double open = 0.0, open32 = 0.0;
+  for (int g = threadIdx.x; g < S.G; g += kRedBlock) {
+    open = fmax(open, S.ctrl[g].done ? 0.0 : 1.0);
+    open32 = fmax(open32, S.skip32[g] ? 0.0 : 1.0);
+  }
   open = block_reduce(open, sh, OpMax());
-  if (threadIdx.x == 0) S.sctrl->all_done = open > 0.0 ? 0 : 1;
+  open32 = block_reduce(open32, sh, OpMax());
+  if (threadIdx.x == 0) {
+    S.sctrl->all_done = open > 0.0 ? 0 : 1;
+    S.sctrl->no32 = open32 > 0.0 ? 0 : 1;
+  }
 }
 
 __global__ void __launch_bounds__(kRedBlock) sum_stage(Solver S, const double* x) {
@@ -332,6 +349,7 @@ void free_solver(Plan& p) {
   Solver* S = p.solver;
   if (S == nullptr) return;
   if (S->exec) (void)hipGraphExecDestroy(S->exec);
+  if (S->exec64) (void)hipGraphExecDestroy(S->exec64);
   for (void* q : {(void*)S->x, (void*)S->z, (void*)S->w, (void*)S->part, (void*)S->sums, (void*)S->bgraph,
                   (void*)S->bsub, (void*)S->gblk0, (void*)S->gnblk, (void*)S->voff, (void*)S->gn,
                   (void*)S->skip64, (void*)S->skip32, (void*)S->ctrl, (void*)S->sctrl})
@@ -414,6 +432,7 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
   sc.tol = tol;
   sc.switch_tol = o.switch_tol;
   sc.shift = o.shift;
+  sc.no32 = o.schedule == STTSV_SOLVE_FP32_FP64 ? 0 : 1;
   if (hipMemcpyAsync(S.ctrl, c.data(), sizeof(GCtrl) * G, hipMemcpyHostToDevice, S.s) != hipSuccess ||
       hipMemcpyAsync(S.sctrl, &sc, sizeof(SCtrl), hipMemcpyHostToDevice, S.s) != hipSuccess ||
       hipMemcpyAsync(S.skip64, s64.data(), 4 * G, hipMemcpyHostToDevice, S.s) != hipSuccess ||
@@ -440,42 +459,61 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
   hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
   if (hipGetLastError() != hipSuccess) return STTSV_EHIP;
 
-  // iterations: captured graph of check_every iterations, or direct launches
+  // iterations: captured graph of check_every iterations, or direct launches.
+  // Under the FP32 -> FP64 schedule, once no open graph runs FP32 series any
+  // more (a graph never switches back) the FP32 launches would all exit at
+  // once: the remaining iterations run the FP64-only sequence instead, which
+  // computes the same bits.
   const int K = o.check_every;
-  if (o.use_graph && (S.exec == nullptr || S.graph_iters != K || S.graph_sched != o.schedule)) {
-    if (S.exec) {
-      (void)hipGraphExecDestroy(S.exec);
-      S.exec = nullptr;
+  auto capture = [&](int sched, hipGraphExec_t* exec) -> int {
+    if (*exec) {
+      (void)hipGraphExecDestroy(*exec);
+      *exec = nullptr;
     }
     if (hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal) != hipSuccess) return STTSV_EHIP;
     hipError_t e = hipSuccess;
-    for (int t = 0; t < K && e == hipSuccess; ++t) e = enqueue_iteration(p, S, o.schedule);
+    for (int t = 0; t < K && e == hipSuccess; ++t) e = enqueue_iteration(p, S, sched);
     const hipError_t e2 = hipStreamEndCapture(S.s, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       return STTSV_EHIP;
     }
-    e = hipGraphInstantiate(&S.exec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      S.exec = nullptr;
+      *exec = nullptr;
       return STTSV_EHIP;
     }
+    return STTSV_OK;
+  };
+  if (o.use_graph && (S.exec == nullptr || S.graph_iters != K || S.graph_sched != o.schedule)) {
+    if ((rc = capture(o.schedule, &S.exec)) != STTSV_OK) return rc;
     S.graph_iters = K;
     S.graph_sched = o.schedule;
   }
+  bool only64 = o.schedule != STTSV_SOLVE_FP32_FP64;
   for (;;) {
+    const int sched = only64 ? STTSV_SOLVE_FP64 : o.schedule;
     if (o.use_graph) {
-      if (hipGraphLaunch(S.exec, S.s) != hipSuccess) return STTSV_EHIP;
+      hipGraphExec_t* ex = &S.exec;
+      if (sched != o.schedule) {
+        if (S.exec64 == nullptr || S.graph64_iters != K) {
+          if ((rc = capture(STTSV_SOLVE_FP64, &S.exec64)) != STTSV_OK) return rc;
+          S.graph64_iters = K;
+        }
+        ex = &S.exec64;
+      }
+      if (hipGraphLaunch(*ex, S.s) != hipSuccess) return STTSV_EHIP;
     } else {
       for (int t = 0; t < K; ++t)
-        if (enqueue_iteration(p, S, o.schedule) != hipSuccess) return STTSV_EHIP;
+        if (enqueue_iteration(p, S, sched) != hipSuccess) return STTSV_EHIP;
     }
     if (hipMemcpyAsync(S.hsctrl, S.sctrl, sizeof(SCtrl), hipMemcpyDeviceToHost, S.s) != hipSuccess) return STTSV_EHIP;
     if (hipStreamSynchronize(S.s) != hipSuccess) return STTSV_EHIP;
     if (S.hsctrl->all_done) break;
+    only64 = only64 || S.hsctrl->no32 != 0;
   }
   if (hipMemcpy(S.hctrl, S.ctrl, sizeof(GCtrl) * G, hipMemcpyDeviceToHost) != hipSuccess) return STTSV_EHIP;
 

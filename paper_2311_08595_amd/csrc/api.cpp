@@ -285,17 +285,19 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
       case STTSV_Q_CONTRIB: {
         if (count != p.nnz) return STTSV_EINVAL;
         std::vector<double> c(p.nnz), v(p.nnz);
-        if (hipStreamSynchronize(p.stream) != hipSuccess ||
-            (p.nnz > 0 && hipMemcpy(c.data(), p.d_contrib, sizeof(double) * p.nnz, hipMemcpyDeviceToHost) != hipSuccess))
-          return STTSV_EHIP;
+        if (hipStreamSynchronize(p.stream) != hipSuccess) return STTSV_EHIP;
         if (p.contrib_compact) {
           // an FP32 apply left 32-bit words (upper halves of FP64 values)
-          const uint32_t* w = reinterpret_cast<const uint32_t*>(c.data());
+          std::vector<uint32_t> w(p.nnz);
+          if (p.nnz > 0 && hipMemcpy(w.data(), p.d_contrib32, sizeof(uint32_t) * p.nnz, hipMemcpyDeviceToHost) != hipSuccess)
+            return STTSV_EHIP;
           for (int64_t q = 0; q < p.nnz; ++q) {
             const uint64_t u = static_cast<uint64_t>(w[p.glist[q]]) << 32;
             std::memcpy(&v[q], &u, sizeof(double));
           }
         } else {
+          if (p.nnz > 0 && hipMemcpy(c.data(), p.d_contrib, sizeof(double) * p.nnz, hipMemcpyDeviceToHost) != hipSuccess)
+            return STTSV_EHIP;
           for (int64_t q = 0; q < p.nnz; ++q) v[q] = c[p.glist[q]];
         }
         return copy_out<double, double>(v, out, count);

@@ -238,10 +238,10 @@ hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s) {
   return launch_permute(p, x, nullptr, s, false);
 }
 
-// The edge-launch arguments of one apply: compact (FP32 apply) or not.
-static EdgeCall edge_call(Plan& p, const double* xr, const int32_t* done, const int32_t* gskip, bool compact) {
-  return EdgeCall{xr, p.d_contrib, done, gskip, compact ? p.d_xr32 : nullptr,
-                  compact ? reinterpret_cast<uint32_t*>(p.d_contrib) : nullptr};
+// The edge-launch arguments: compact (FP32 x from x32, 32-bit contributions)
+// when x32 is given, else FP64 x and contributions.
+static EdgeCall edge_call(Plan& p, const double* xr, const int32_t* done, const int32_t* gskip, const float* x32) {
+  return EdgeCall{xr, p.d_contrib, done, gskip, x32, x32 != nullptr ? p.d_contrib32 : nullptr};
 }
 
 // c.x: the caller's x for the permute stage, the rank-ordered copy for edge stages
@@ -270,7 +270,8 @@ static hipError_t launch_stage_call(Plan& p, const Stage& S, const EdgeCall& c, 
     return fn ? fn(c, G.d_bks, G.d_tasks, G.ntasks, G.lds, s) : hipErrorInvalidValue;
   }
   const size_t l = static_cast<size_t>(S.index);
-  const void* in = l == 0 ? static_cast<const void*>(p.d_contrib) : p.d_partials[l - 1];
+  const void* in = l > 0 ? static_cast<const void*>(p.d_partials[l - 1])
+                         : compact ? static_cast<const void*>(p.d_contrib32) : static_cast<const void*>(p.d_contrib);
   double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
   return launch_reduce_level(p.levels[l], in, y, next, c.done, s, false, compact && l == 0);
 }
@@ -280,7 +281,8 @@ hipError_t launch_stage(Plan& p, int stage, const double* x, double* y, int prec
   const Stage& S = p.stages[precision == STTSV_PREC_FP32 ? 1 : 0][stage];
   const bool compact = precision == STTSV_PREC_FP32 && p.compact_ok;
   if (S.type != 2) p.contrib_compact = compact;
-  return launch_stage_call(p, S, edge_call(p, S.type == 3 ? x : p.d_xr, done, nullptr, compact), y, s);
+  return launch_stage_call(p, S, edge_call(p, S.type == 3 ? x : p.d_xr, done, nullptr, compact ? p.d_xr32 : nullptr),
+                           y, s);
 }
 
 hipError_t launch_sttsv(Plan& p, const double* x, double* y, int precision,
@@ -301,14 +303,15 @@ int init_lanes(Plan& p) {
 
 // Edge stages of np precisions (precs[i] with per-graph skip flags skips[i])
 // inside one fork/join of the stream lanes.
+// x32 (nullable): the FP32 stages run compact, gathering from it.
 static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, const int32_t* const* skips, int np,
-                                   const int32_t* done, hipStream_t s, XOrder order, bool compact) {
+                                   const int32_t* done, hipStream_t s, XOrder order, const float* x32) {
   const double* xr = order == XOrder::kRank ? x : p.d_xr;
   const bool multi = !(p.flags & STTSV_FLAG_ONE_STREAM) && p.ev_fork != nullptr;
   int nl = 1;
   if (multi)
     for (int i = 0; i < np; ++i) nl = std::max(nl, p.lanes[precs[i] == STTSV_PREC_FP32 ? 1 : 0]);
-  hipError_t e = order == XOrder::kVertex ? launch_permute(p, x, done, s, compact) : hipSuccess;
+  hipError_t e = order == XOrder::kVertex ? launch_permute(p, x, done, s, x32 != nullptr) : hipSuccess;
   if (e != hipSuccess) return e;
   if (nl > 1) {
     // fork: every helper lane starts after the work already on s
@@ -319,7 +322,7 @@ static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, c
   for (int i = 0; i < np && e == hipSuccess; ++i) {
     const int seq = precs[i] == STTSV_PREC_FP32 ? 1 : 0;
     const bool lanes = nl > 1 && p.lanes[seq] > 1;
-    const EdgeCall c = edge_call(p, xr, done, skips[i], compact);
+    const EdgeCall c = edge_call(p, xr, done, skips[i], precs[i] == STTSV_PREC_FP32 ? x32 : nullptr);
     for (const Stage& S : p.stages[seq]) {
       if (S.type == 2 || S.type == 3) continue;
       const hipStream_t ls = lanes && S.lane > 0 ? p.aux[S.lane - 1] : s;
@@ -347,20 +350,34 @@ hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* 
   if (compact && (precision != STTSV_PREC_FP32 || order != XOrder::kVertex || !p.compact_ok))
     return hipErrorInvalidValue;
   p.contrib_compact = compact;
-  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order, compact);
+  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order, compact ? p.d_xr32 : nullptr);
 }
 
 hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
-                             const int32_t* skip64, hipStream_t s) {
+                             const int32_t* skip64, hipStream_t s, const float* x32) {
   const int precs[2] = {STTSV_PREC_FP32, STTSV_PREC_FP64};
   const int32_t* skips[2] = {skip32, skip64};
+  if (x32 != nullptr && !p.compact_ok) return hipErrorInvalidValue;
   p.contrib_compact = false;
-  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank, false);
+  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank, x32);
+}
+
+hipError_t launch_reduction_phased(Plan& p, double* y, const int32_t* phase32, const int32_t* done, hipStream_t s,
+                                   bool rank_out) {
+  for (size_t l = 0; l < p.levels.size(); ++l) {
+    double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
+    const hipError_t e = l == 0 ? launch_reduce_level0_phased(p.levels[0], p.d_contrib, p.d_contrib32, phase32, y,
+                                                              next, done, s, rank_out)
+                                : launch_reduce_level(p.levels[l], p.d_partials[l - 1], y, next, done, s, rank_out);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out, bool compact) {
   for (size_t l = 0; l < p.levels.size(); ++l) {
-    const void* in = l == 0 ? static_cast<const void*>(p.d_contrib) : p.d_partials[l - 1];
+    const void* in = l > 0 ? static_cast<const void*>(p.d_partials[l - 1])
+                           : compact ? static_cast<const void*>(p.d_contrib32) : static_cast<const void*>(p.d_contrib);
     double* next = l < p.d_partials.size() ? p.d_partials[l] : nullptr;
     const hipError_t e = launch_reduce_level(p.levels[l], in, y, next, done, s, rank_out, compact && l == 0);
     if (e != hipSuccess) return e;

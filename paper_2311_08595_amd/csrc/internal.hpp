@@ -64,9 +64,9 @@ struct EdgeCall {
   double* contrib;      // per-incidence contributions (one region per vertex block)
   const int32_t* done;  // whole launch is skipped when *done != 0 (nullable)
   const int32_t* gskip; // per-graph skip flags indexed by BucketDesc::gid (nullable)
-  // compact FP32 apply (both null otherwise): FP32-series kernels gather x
-  // from x32, and every kernel stores its contribution as the upper 32 bits
-  // of the FP64 value, rounded (contrib32 aliases contrib)
+  // compact FP32 series (both null otherwise): FP32-series kernels gather x
+  // from x32 and store each contribution as the upper 32 bits of its FP64
+  // value, rounded, at the same place in contrib32 (a buffer of its own)
   const float* x32;
   uint32_t* contrib32;
 };
@@ -266,10 +266,13 @@ struct Plan {
   // whenever the places change.
   std::vector<int4> l0_wg;
   std::vector<int32_t> l0_n1;
+  std::vector<int32_t> l0_graph;     // graph of each level-0 workgroup's block
+  std::vector<int32_t> block_graph;  // graph of every vertex block
   std::vector<int64_t> l0_base, l0_terms;
   int32_t* d_gid = nullptr;       // graph of every edge (batched plans only)
   double* d_wgt = nullptr;        // per canonical edge w(e)/|beta(e)| (r-1)! (edge-weighted plans only)
   double* d_contrib = nullptr;    // contributions, one region per vertex block
+  uint32_t* d_contrib32 = nullptr; // the same places as 32-bit words (compact FP32 series)
   bool contrib_compact = false;   // the last apply stored 32-bit contributions (FP32 apply)
   bool compact_ok = false;        // every FP32-list edge stage (k >= 2) runs FP32 series: FP32 applies run compact
   std::vector<GenGroup> groups;   // fused generic launches (both precisions)
@@ -325,13 +328,19 @@ enum class XOrder { kVertex, kRank, kCopied };
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
                         hipStream_t s, XOrder order = XOrder::kVertex, bool compact = false);
 // rank_out: write y in degree-rank order instead of vertex order.
-// FP32- and FP64-series edge stages (x already in rank order) inside one
-// fork/join, each gated by its own per-graph skip flags: the solver's mixed
-// schedule, where each graph runs one of the two per iteration.
-hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
-                             const int32_t* skip64, hipStream_t s);
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false,
                             bool compact = false);
+// The solver's mixed schedule with compact FP32 series: graph g's level-0
+// workgroups read 32-bit words when phase32[g] == 0 (the graph runs FP32
+// series this iteration), FP64 contributions otherwise.
+hipError_t launch_reduction_phased(Plan& p, double* y, const int32_t* phase32, const int32_t* done, hipStream_t s,
+                                   bool rank_out);
+// FP32- and FP64-series edge stages (x already in rank order) inside one
+// fork/join, each gated by its own per-graph skip flags: the solver's mixed
+// schedule, where each graph runs one of the two per iteration.  With x32
+// (the iterate in rank order, rounded to FP32) the FP32 stages run compact.
+hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
+                             const int32_t* skip64, hipStream_t s, const float* x32);
 
 // x into degree-rank order (the copy the edge kernels gather from)
 hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s);
@@ -351,6 +360,9 @@ int cp_descent(Plan& p, int32_t R, double* A, double* lambda, int32_t iters, dou
 // reduction kernels (reduce.hip)
 hipError_t launch_reduce_level(const ReduceLevel& L, const void* in, double* y, double* next,
                                const int32_t* done, hipStream_t s, bool rank_out = false, bool compact = false);
+hipError_t launch_reduce_level0_phased(const ReduceLevel& L, const double* in64, const uint32_t* in32,
+                                       const int32_t* phase32, double* y, double* next, const int32_t* done,
+                                       hipStream_t s, bool rank_out);
 
 // autotuner (tune.cpp)
 int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t* tuned);

@@ -48,6 +48,7 @@ struct Solver {
   int32_t n = 0, G = 0, nblk = 0;
   hipStream_t s = nullptr;
   double* x = nullptr;        // current iterates, max-normalised per graph
+  float* x32 = nullptr;       // the same rounded to FP32 (compact FP32 series of the mixed schedule)
   double* z = nullptr;
   double* w = nullptr;
   double* part = nullptr;     // per-block partials (4 per block)
@@ -154,12 +155,17 @@ __global__ void __launch_bounds__(kRedBlock) init_final(Solver S) {
   }
 }
 
-__global__ void __launch_bounds__(kRedBlock) scale_into(Solver S, const double* src, double* dst) {
+// dst = src / max per graph (and rounded to FP32 into dst32 when given)
+__global__ void __launch_bounds__(kRedBlock) scale_into(Solver S, const double* src, double* dst, float* dst32) {
   const VBlock vb = vblock(S);
   const GCtrl& c = S.ctrl[vb.g];
   if (c.done) return;
   const double f = c.inv_wmax;
-  for (int v = vb.v0; v < vb.vend; v += vb.stride) dst[v] = src[v] * f;
+  for (int v = vb.v0; v < vb.vend; v += vb.stride) {
+    const double t = src[v] * f;
+    dst[v] = t;
+    if (dst32 != nullptr) dst32[v] = static_cast<float>(t);
+  }
 }
 
 // The solver keeps x, z, w in degree-rank order (position q holds vertex
@@ -324,20 +330,29 @@ __global__ void __launch_bounds__(kRedBlock) sum_final(Solver S) {
   if (threadIdx.x == 0) S.sums[g] = acc;
 }
 
+// FP32-series iterations of the mixed schedule run compact (FP32 x,
+// 32-bit contributions) when every FP32-list edge stage has FP32 series.
+bool compact_mixed(const Plan& p, int schedule) { return schedule == STTSV_SOLVE_FP32_FP64 && p.compact_ok; }
+
 // One NQZ iteration (all launches on S.s).
 hipError_t enqueue_iteration(Plan& p, Solver& S, int schedule) {
   hipError_t e;
   const int32_t* all_done = &S.sctrl->all_done;
+  const bool cmp = compact_mixed(p, schedule);
   if (schedule == STTSV_SOLVE_FP32_FP64)
-    e = launch_edges_both(p, S.x, all_done, S.skip32, S.skip64, S.s);
+    e = launch_edges_both(p, S.x, all_done, S.skip32, S.skip64, S.s, cmp ? S.x32 : nullptr);
   else
     e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s, XOrder::kRank);
   if (e != hipSuccess) return e;
-  if ((e = launch_reduction(p, S.z, all_done, S.s, true)) != hipSuccess) return e;
+  // a graph's level-0 workgroups read words while it runs FP32 series (skip32 == 0)
+  e = cmp ? launch_reduction_phased(p, S.z, S.skip32, all_done, S.s, true)
+          : launch_reduction(p, S.z, all_done, S.s, true);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((nqz_stats<true>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<true>), dim3(S.G), dim3(kRedBlock), 0, S.s, S);
   if (S.G > 1) hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
-  hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
+  hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x,
+                     cmp ? S.x32 : nullptr);
   return hipGetLastError();
 }
 
@@ -350,7 +365,7 @@ void free_solver(Plan& p) {
   if (S == nullptr) return;
   if (S->exec) (void)hipGraphExecDestroy(S->exec);
   if (S->exec64) (void)hipGraphExecDestroy(S->exec64);
-  for (void* q : {(void*)S->x, (void*)S->z, (void*)S->w, (void*)S->part, (void*)S->sums, (void*)S->bgraph,
+  for (void* q : {(void*)S->x, (void*)S->x32, (void*)S->z, (void*)S->w, (void*)S->part, (void*)S->sums, (void*)S->bgraph,
                   (void*)S->bsub, (void*)S->gblk0, (void*)S->gnblk, (void*)S->voff, (void*)S->gn,
                   (void*)S->skip64, (void*)S->skip32, (void*)S->ctrl, (void*)S->sctrl})
     (void)hipFree(q);
@@ -383,7 +398,7 @@ static int ensure_solver(Plan& p) {
   const size_t nb = size_t(p.n) * sizeof(double);
   if (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) return STTSV_EHIP;
   auto alloc = [](auto** ptr, size_t bytes) { return hipMalloc(reinterpret_cast<void**>(ptr), bytes) == hipSuccess; };
-  if (!alloc(&S->x, nb) || !alloc(&S->z, nb) || !alloc(&S->w, nb) ||
+  if (!alloc(&S->x, nb) || !alloc(&S->x32, nb / 2) || !alloc(&S->z, nb) || !alloc(&S->w, nb) ||
       !alloc(&S->part, 4 * sizeof(double) * S->nblk) || !alloc(&S->sums, sizeof(double) * G) ||
       !alloc(&S->bgraph, 4 * S->nblk) || !alloc(&S->bsub, 4 * S->nblk) || !alloc(&S->gblk0, 4 * G) ||
       !alloc(&S->gnblk, 4 * G) || !alloc(&S->voff, 4 * G) || !alloc(&S->gn, 4 * G) ||
@@ -456,7 +471,8 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
   hipLaunchKernelGGL((nqz_stats<false>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<false>), dim3(G), dim3(kRedBlock), 0, S.s, S);
   if (G > 1) hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
-  hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x);
+  hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x,
+                     compact_mixed(p, o.schedule) ? S.x32 : nullptr);
   if (hipGetLastError() != hipSuccess) return STTSV_EHIP;
 
   // iterations: captured graph of check_every iterations, or direct launches.

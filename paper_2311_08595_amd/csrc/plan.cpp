@@ -108,6 +108,7 @@ HostLevel level0_schedule(Plan& P, const HostLevel& L, const std::vector<int32_t
   P.l0_n1.clear();
   P.l0_base.clear();
   P.l0_terms.clear();
+  P.l0_graph.clear();
   for (const Wg& w : wgs) {
     std::vector<int64_t> v(bc[w.block].begin() + w.first, bc[w.block].begin() + w.first + w.count);
     std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t q) { return L.len[a] > L.len[q]; });
@@ -120,6 +121,7 @@ HostLevel level0_schedule(Plan& P, const HostLevel& L, const std::vector<int32_t
     P.l0_wg.push_back(make_int4(static_cast<int32_t>(R.len.size()), static_cast<int32_t>(cnt[0]),
                                 static_cast<int32_t>(cnt[1]), static_cast<int32_t>(cnt[2])));
     P.l0_n1.push_back(static_cast<int32_t>(cnt[3]));
+    P.l0_graph.push_back(P.block_graph[w.block]);
     P.l0_base.push_back(base == INT64_MAX ? 0 : base);
     P.l0_terms.push_back(w.terms);
     for (int64_t c : v) {
@@ -163,7 +165,7 @@ int stage_level0(Plan& P) {
     const int32_t nr = static_cast<int32_t>(ranges.size()) - r0;
     if (nr > kStageRuns) return STTSV_EINVAL;
     wg[2 * w] = P.l0_wg[w];
-    wg[2 * w + 1] = make_int4(P.l0_n1[w], r0, nr, 0);
+    wg[2 * w + 1] = make_int4(P.l0_n1[w], r0, nr, P.l0_graph[w]);
   }
   if (hipMemcpy(D.d_wg, wg.data(), sizeof(int4) * wg.size(), hipMemcpyHostToDevice) != hipSuccess ||
       (!ranges.empty() &&
@@ -279,6 +281,7 @@ void free_plan(Plan* p) {
   (void)hipFree(p->d_rid);
   (void)hipFree(p->d_xr);
   (void)hipFree(p->d_xr32);
+  (void)hipFree(p->d_contrib32);
   (void)hipFree(p->d_loc);
   (void)hipFree(p->d_gid);
   (void)hipFree(p->d_wgt);
@@ -842,10 +845,18 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
     P->region.assign(1, 0);
     int64_t nv = 0;                   // vertices in the current block
     int64_t cnt[4] = {0, 0, 0, 0};    // its level-0 chunks per lane class
+    int g = 0;
     for (int32_t u = 0; u < n; ++u) {
       int64_t with[4] = {cnt[0], cnt[1], cnt[2], cnt[3]};
       add_chunks(deg[u], with);
-      if (nv > 0 && (acc + deg[u] > kStageTerms || stage_passes(with) > kStagePasses)) {
+      // a block holds one graph's vertices only: its level-0 workgroups can
+      // then read the contribution format of that graph's solver phase
+      bool new_graph = false;
+      while (g + 1 < G && u >= P->graphs[g + 1].voff) {
+        ++g;
+        new_graph = true;
+      }
+      if (nv > 0 && (new_graph || acc + deg[u] > kStageTerms || stage_passes(with) > kStagePasses)) {
         P->region.push_back(P->region.back() + acc);
         ++b;
         acc = 0;
@@ -859,6 +870,10 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
       for (int q = 0; q < 4; ++q) cnt[q] = with[q];
     }
     P->region.push_back(nnz);
+    // graph of every block (blocks never straddle graphs)
+    P->block_graph.assign(P->region.size() - 1, 0);
+    for (int gi = 0; gi < G; ++gi)
+      for (int32_t v = 0; v < P->graphs[gi].n; ++v) P->block_graph[vblock[P->graphs[gi].voff + v]] = gi;
   }
 
   // ---- reduction schedule
@@ -927,6 +942,7 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   for (int32_t q = 0; q < n; ++q) rpos[rid[q]] = q;
   if ((rc = upload<double>(&P->d_xr, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<float>(&P->d_xr32, nullptr, n, &P->device_bytes)) != STTSV_OK) return fail(rc);
+  if ((rc = upload<uint32_t>(&P->d_contrib32, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<int32_t>(&P->d_loc, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if ((rc = upload<double>(&P->d_contrib, nullptr, nnz, &P->device_bytes)) != STTSV_OK) return fail(rc);
   if (G > 1 && (rc = upload(&P->d_gid, gid.data(), gid.size(), &P->device_bytes)) != STTSV_OK) return fail(rc);

@@ -158,17 +158,13 @@ __device__ __forceinline__ void stage_pass(int G, int2 d, const double* st, doub
   }
 }
 
+// One level-0 workgroup: stage its contributions (format In) into LDS, then
+// its passes.
 template <typename In>
-__global__ void __launch_bounds__(kStageThreads) reduce_level0(const int2* __restrict__ desc,
-                                                               const int4* __restrict__ wg,
-                                                               const int2* __restrict__ ranges,
-                                                               const uint16_t* __restrict__ lpos,
-                                                               const In* __restrict__ in,
-                                                               double* __restrict__ y, double* __restrict__ next,
-                                                               const int32_t* done) {
-  if (done != nullptr && *done) return;
-  __shared__ double st[kStageTerms];
-  const int4 a = wg[2 * blockIdx.x], b = wg[2 * blockIdx.x + 1];
+__device__ __forceinline__ void level0_body(double* st, const int2* __restrict__ desc, int4 a, int4 b,
+                                            const int2* __restrict__ ranges, const uint16_t* __restrict__ lpos,
+                                            const In* __restrict__ in, double* __restrict__ y,
+                                            double* __restrict__ next) {
   int2 d[kStagePasses];
 #pragma unroll
   for (int p = 0; p < kStagePasses; ++p) {
@@ -189,6 +185,40 @@ __global__ void __launch_bounds__(kStageThreads) reduce_level0(const int2* __res
   }
 }
 
+template <typename In>
+__global__ void __launch_bounds__(kStageThreads) reduce_level0(const int2* __restrict__ desc,
+                                                               const int4* __restrict__ wg,
+                                                               const int2* __restrict__ ranges,
+                                                               const uint16_t* __restrict__ lpos,
+                                                               const In* __restrict__ in,
+                                                               double* __restrict__ y, double* __restrict__ next,
+                                                               const int32_t* done) {
+  if (done != nullptr && *done) return;
+  __shared__ double st[kStageTerms];
+  level0_body<In>(st, desc, wg[2 * blockIdx.x], wg[2 * blockIdx.x + 1], ranges, lpos, in, y, next);
+}
+
+// Mixed formats: the workgroup's block belongs to graph b.w, whose
+// contributions this iteration are 32-bit words when phase32[b.w] == 0 (the
+// graph ran FP32 series) and FP64 otherwise (uniform per workgroup).
+__global__ void __launch_bounds__(kStageThreads) reduce_level0_phased(const int2* __restrict__ desc,
+                                                                      const int4* __restrict__ wg,
+                                                                      const int2* __restrict__ ranges,
+                                                                      const uint16_t* __restrict__ lpos,
+                                                                      const double* __restrict__ in64,
+                                                                      const uint32_t* __restrict__ in32,
+                                                                      const int32_t* __restrict__ phase32,
+                                                                      double* __restrict__ y,
+                                                                      double* __restrict__ next, const int32_t* done) {
+  if (done != nullptr && *done) return;
+  __shared__ double st[kStageTerms];
+  const int4 a = wg[2 * blockIdx.x], b = wg[2 * blockIdx.x + 1];
+  if (phase32[b.w] == 0)
+    level0_body<uint32_t>(st, desc, a, b, ranges, lpos, in32, y, next);
+  else
+    level0_body<double>(st, desc, a, b, ranges, lpos, in64, y, next);
+}
+
 }  // namespace
 
 template <typename In>
@@ -205,6 +235,16 @@ hipError_t launch_level(const ReduceLevel& L, const In* in, double* y, double* n
     hipLaunchKernelGGL((reduce_level<true, In>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
   else
     hipLaunchKernelGGL((reduce_level<false, In>), grid, dim3(256), 0, s, L.d_desc, L.nchunks, in, y, next, done);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_level0_phased(const ReduceLevel& L, const double* in64, const uint32_t* in32,
+                                       const int32_t* phase32, double* y, double* next, const int32_t* done,
+                                       hipStream_t s, bool rank_out) {
+  if (L.nchunks == 0) return hipSuccess;
+  if (L.d_wg == nullptr) return hipErrorInvalidValue;    // level 0 is always staged when it has chunks
+  hipLaunchKernelGGL(reduce_level0_phased, dim3(static_cast<unsigned>(L.nwg)), dim3(kStageThreads), 0, s,
+                     L.d_desc0[rank_out ? 1 : 0], L.d_wg, L.d_ranges, L.d_lpos, in64, in32, phase32, y, next, done);
   return hipGetLastError();
 }
 

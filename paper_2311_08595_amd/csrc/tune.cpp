@@ -169,9 +169,7 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
   // runs them
   if (launch_stage(p, 0, x, nullptr, STTSV_PREC_FP32, nullptr, p.stream) != hipSuccess) return STTSV_EHIP;
   const EdgeCall c64{p.d_xr, p.d_contrib, nullptr, nullptr, nullptr, nullptr};
-  const EdgeCall c32 = p.compact_ok ? EdgeCall{p.d_xr, p.d_contrib, nullptr, nullptr, p.d_xr32,
-                                               reinterpret_cast<uint32_t*>(p.d_contrib)}
-                                    : c64;
+  const EdgeCall c32 = p.compact_ok ? EdgeCall{p.d_xr, p.d_contrib, nullptr, nullptr, p.d_xr32, p.d_contrib32} : c64;
   int count = 0;
   for (Bucket& B : p.buckets) {
     if (B.k < 4) continue;

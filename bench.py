@@ -183,18 +183,21 @@ SMALL_KIND = {2: 0, 3: 1, 4: 2, 5: 3, 6: 4, 7: 5}
 
 def stage_kernel(s, prec, r):
     """Kernel name (template form, as the profiler prints it) and grid size
-    of a stage; grid None where one launch per apply has that name."""
-    t = "double" if prec == "fp64" else "float"
+    of a stage; grid None where one launch per apply has that name.  FP32
+    applies run the compact variants (template flag true; the workloads with
+    committed counters have no FP64-fallback size under FP32)."""
+    t, cp = ("double", "false") if prec == "fp64" else ("float", "true")
     if s["kind"] == 0 and s["size"] in SMALL_KIND:
-        return "edge_small<%s, %d, %d>" % (t, r - s["size"] + 1, SMALL_KIND[s["size"]]), (s["count"] + 255) // 256 * 256
+        return ("edge_small<%s, %d, %d, %s>" % (t, r - s["size"] + 1, SMALL_KIND[s["size"]], cp),
+                (s["count"] + 255) // 256 * 256)
     if s["kind"] == 1:
-        return "edge_generic<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
+        return "edge_generic<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), None
     if s["kind"] == 4:
-        return "edge_coop<%s, %d, %d>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]]), None
+        return "edge_coop<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), None
     if s["kind"] == 2:
         if s["size"] == 0:
-            return "reduce_level0", None
-        return "reduce_level<false>", s["count"] * 8
+            return "reduce_level0<%s>" % ("double" if prec == "fp64" else "unsigned int"), None
+        return "reduce_level<false, double>", s["count"] * 8
     if s["kind"] == 3:
         return "permute_x", (s["count"] + 255) // 256 * 256
     return None, None
@@ -983,6 +986,29 @@ def main():
             except Exception as exc:
                 solve["sshopm_fp64"] = {"error": str(exc)}
                 log("[bench]   SS-HOPM failed: %s" % exc)
+            try:   # symmetric CP decomposition: one objective + gradient (R FP64 STTSVs) and a short descent
+                R = 4
+                gen = torch.Generator(device="cuda").manual_seed(7)
+                A = torch.rand((R, n2), dtype=torch.float64, device="cuda", generator=gen)
+                A /= A.norm(dim=1, keepdim=True)
+                lam = torch.ones(R, dtype=torch.float64, device="cuda")
+                p2.cp_objective_grad(A, lam)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    f, _, _ = p2.cp_objective_grad(A, lam)
+                eval_ms = (time.perf_counter() - t0) * 1e3 / 5
+                t0 = time.perf_counter()
+                ci = p2.cp_descent(A.clone(), lam.clone(), 10, 1.0)
+                desc_s = time.perf_counter() - t0
+                solve["sym_cp_r4"] = dict(eval_ms=eval_ms, sttsv_ms=solve.get("sshopm_fp64", {}).get("sttsv_ms"),
+                                          descent_10_s=desc_s, f0=ci["f0"], f=ci["f"], norm2=ci["norm2"],
+                                          halvings=ci["halvings"])
+                log("[bench]   symmetric CP (R=4): %.3f ms per objective+gradient; 10 descent steps %.4f s, "
+                    "f/||B||^2 %.4f -> %.4f" % (eval_ms, desc_s, ci["f0"] / ci["norm2"], ci["f"] / ci["norm2"]))
+            except Exception as exc:
+                solve["sym_cp_r4"] = {"error": str(exc)}
+                log("[bench]   symmetric CP failed: %s" % exc)
         out["solve"] = solve
     if not a.no_batch:
         out["batched"] = bench_batch(a)

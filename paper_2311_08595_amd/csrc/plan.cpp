@@ -32,12 +32,101 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
 
 namespace sttsv {
 namespace {
+
+// ---- host parallelism.  Every parallel loop below writes disjoint outputs
+// or combines per-chunk results in a fixed order, so the layout is the same
+// whatever the thread count.
+int host_threads() {
+  static const int t = [] {
+    const unsigned h = std::thread::hardware_concurrency();
+    return static_cast<int>(std::max(1u, std::min(16u, h)));
+  }();
+  return t;
+}
+
+thread_local bool t_in_parallel = false;   // loops nested in a parallel loop run inline
+
+// f(chunk, begin, end) over [0, n) cut into at most host_threads() contiguous
+// chunks (chunk index in order); small ranges, and loops inside another
+// parallel loop, run inline.
+template <typename F>
+void parallel_chunks(int64_t n, F&& f, int64_t min_per_chunk = 1 << 15) {
+  const int64_t T = t_in_parallel ? 1
+                                  : std::max<int64_t>(1, std::min<int64_t>(host_threads(),
+                                                                           n / std::max<int64_t>(1, min_per_chunk)));
+  if (T <= 1) {
+    f(0, int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (int64_t t = 1; t < T; ++t)
+    th.emplace_back([&, t] {
+      t_in_parallel = true;
+      f(static_cast<int>(t), n * t / T, n * (t + 1) / T);
+    });
+  t_in_parallel = true;
+  f(0, int64_t(0), n / T);
+  t_in_parallel = false;
+  for (auto& x : th) x.join();
+}
+int chunk_count(int64_t n, int64_t min_per_chunk = 1 << 15) {
+  if (t_in_parallel) return 1;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / std::max<int64_t>(1, min_per_chunk))));
+}
+
+// Sort with a strict total order (equal keys impossible), in parallel: sorted
+// chunks merged pairwise.  The order is unique, so the result equals
+// std::sort's.
+template <typename T, typename Less>
+void parallel_sort(std::vector<T>& v, Less less) {
+  const int64_t n = static_cast<int64_t>(v.size());
+  const int T0 = chunk_count(n, 1 << 16);
+  if (T0 <= 1) {
+    std::sort(v.begin(), v.end(), less);
+    return;
+  }
+  std::vector<int64_t> cut(T0 + 1);
+  for (int t = 0; t <= T0; ++t) cut[t] = n * t / T0;
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < T0; ++t)
+      th.emplace_back([&, t] { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1], less); });
+    for (auto& x : th) x.join();
+  }
+  std::vector<T> tmp(v.size());
+  std::vector<T>* src = &v;
+  std::vector<T>* dst = &tmp;
+  while (cut.size() > 2) {
+    std::vector<int64_t> next;
+    std::vector<std::thread> th;
+    for (size_t q = 0; q + 1 < cut.size(); q += 2) {
+      if (q + 2 < cut.size()) {
+        const int64_t a = cut[q], b = cut[q + 1], e = cut[q + 2];
+        th.emplace_back([=, &less] {
+          std::merge(src->begin() + a, src->begin() + b, src->begin() + b, src->begin() + e, dst->begin() + a, less);
+        });
+        next.push_back(a);
+      } else {                                  // an odd run out: copied as is
+        const int64_t a = cut[q], e = cut[q + 1];
+        th.emplace_back([=] { std::copy(src->begin() + a, src->begin() + e, dst->begin() + a); });
+        next.push_back(a);
+      }
+    }
+    for (auto& x : th) x.join();
+    next.push_back(n);
+    cut.swap(next);
+    std::swap(src, dst);
+  }
+  if (src != &v) v.swap(*src);
+}
 
 // One level of the reduction schedule (host side).
 struct HostLevel {
@@ -145,27 +234,42 @@ int stage_level0(Plan& P) {
   std::vector<int4> wg(2 * nwg);
   std::vector<int2> ranges;
   std::vector<uint16_t> lpos(P.nnz, 0);
-  std::vector<int32_t> pl;
+  // per workgroup (in parallel): LDS offsets of its terms and the runs of
+  // consecutive places it copies; then the runs are laid out in workgroup order
+  std::vector<std::vector<int2>> wr(nwg);
+  std::vector<int> bad(nwg, 0);
+  parallel_chunks(static_cast<int64_t>(nwg), [&](int, int64_t w0, int64_t w1) {
+    std::vector<int32_t> pl;
+    for (int64_t w = w0; w < w1; ++w) {
+      const int64_t base = P.l0_base[w], terms = P.l0_terms[w];
+      const int64_t cnt[4] = {P.l0_wg[w].y, P.l0_wg[w].z, P.l0_wg[w].w, P.l0_n1[w]};
+      if (terms > kStageTerms || base + terms > P.nnz || stage_passes(cnt) > kStagePasses) {
+        bad[w] = 1;
+        continue;
+      }
+      pl.resize(terms);
+      for (int64_t q = 0; q < terms; ++q) {
+        pl[q] = P.glist[base + q];
+        lpos[pl[q]] = static_cast<uint16_t>(q);
+      }
+      std::sort(pl.begin(), pl.end());
+      for (int64_t i = 0; i < terms; ++i) {
+        if (i > 0 && pl[i] == pl[i - 1]) {          // two terms in one place
+          bad[w] = 1;
+          break;
+        }
+        if (i == 0 || pl[i] != pl[i - 1] + 1) wr[w].push_back(make_int2(pl[i], 0));
+        wr[w].back().y++;
+      }
+      if (wr[w].size() > static_cast<size_t>(kStageRuns)) bad[w] = 1;
+    }
+  }, 16);
   for (size_t w = 0; w < nwg; ++w) {
-    const int64_t base = P.l0_base[w], terms = P.l0_terms[w];
-    const int64_t cnt[4] = {P.l0_wg[w].y, P.l0_wg[w].z, P.l0_wg[w].w, P.l0_n1[w]};
-    if (terms > kStageTerms || base + terms > P.nnz || stage_passes(cnt) > kStagePasses) return STTSV_EINVAL;
-    pl.resize(terms);
-    for (int64_t q = 0; q < terms; ++q) {
-      pl[q] = P.glist[base + q];
-      lpos[pl[q]] = static_cast<uint16_t>(q);
-    }
-    std::sort(pl.begin(), pl.end());
+    if (bad[w]) return STTSV_EINVAL;
     const int32_t r0 = static_cast<int32_t>(ranges.size());
-    for (int64_t i = 0; i < terms; ++i) {
-      if (i > 0 && pl[i] == pl[i - 1]) return STTSV_EINVAL;   // two terms in one place
-      if (i == 0 || pl[i] != pl[i - 1] + 1) ranges.push_back(make_int2(pl[i], 0));
-      ranges.back().y++;
-    }
-    const int32_t nr = static_cast<int32_t>(ranges.size()) - r0;
-    if (nr > kStageRuns) return STTSV_EINVAL;
+    ranges.insert(ranges.end(), wr[w].begin(), wr[w].end());
     wg[2 * w] = P.l0_wg[w];
-    wg[2 * w + 1] = make_int4(P.l0_n1[w], r0, nr, P.l0_graph[w]);
+    wg[2 * w + 1] = make_int4(P.l0_n1[w], r0, static_cast<int32_t>(wr[w].size()), P.l0_graph[w]);
   }
   if (hipMemcpy(D.d_wg, wg.data(), sizeof(int4) * wg.size(), hipMemcpyHostToDevice) != hipSuccess ||
       (!ranges.empty() &&
@@ -365,12 +469,14 @@ void canonicalise(const GraphIn& g, const std::vector<int64_t>& deg, Canon& c) {
   for (int32_t v = 0; v < n; ++v) c.inv_rank[rank[v]] = v;
   const int64_t nnz = g.eptr[g.m];
   c.rk.assign(nnz, 0);
-  for (int64_t e = 0; e < g.m; ++e) {
-    int32_t* a = c.rk.data() + g.eptr[e];
-    const int64_t k = g.eptr[e + 1] - g.eptr[e];
-    for (int64_t j = 0; j < k; ++j) a[j] = rank[g.eidx[g.eptr[e] + j]];
-    std::sort(a, a + k);
-  }
+  parallel_chunks(g.m, [&](int, int64_t e0, int64_t e1) {
+    for (int64_t e = e0; e < e1; ++e) {
+      int32_t* a = c.rk.data() + g.eptr[e];
+      const int64_t k = g.eptr[e + 1] - g.eptr[e];
+      for (int64_t j = 0; j < k; ++j) a[j] = rank[g.eidx[g.eptr[e] + j]];
+      std::sort(a, a + k);
+    }
+  });
   c.order.assign(g.r + 1, {});
   for (int64_t e = 0; e < g.m; ++e) c.order[g.eptr[e + 1] - g.eptr[e]].push_back(e);
   for (int k = 1; k <= g.r; ++k) {
@@ -381,13 +487,15 @@ void canonicalise(const GraphIn& g, const std::vector<int64_t>& deg, Canon& c) {
       int64_t id;
     };
     std::vector<Key> keys(ids.size());
-    for (size_t t = 0; t < ids.size(); ++t) {
-      const int32_t* a = c.rk.data() + g.eptr[ids[t]];
-      const uint64_t r0 = (uint64_t)(uint32_t)a[0];
-      const uint64_t r1 = k > 1 ? (uint64_t)(uint32_t)a[1] : 0;
-      keys[t] = Key{(r0 << 32) | r1, ids[t]};
-    }
-    std::sort(keys.begin(), keys.end(), [&](const Key& x, const Key& y) {
+    parallel_chunks(static_cast<int64_t>(ids.size()), [&](int, int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t) {
+        const int32_t* a = c.rk.data() + g.eptr[ids[t]];
+        const uint64_t r0 = (uint64_t)(uint32_t)a[0];
+        const uint64_t r1 = k > 1 ? (uint64_t)(uint32_t)a[1] : 0;
+        keys[t] = Key{(r0 << 32) | r1, ids[t]};
+      }
+    });
+    parallel_sort(keys, [&](const Key& x, const Key& y) {
       if (x.head != y.head) return x.head < y.head;
       const int32_t* a = c.rk.data() + g.eptr[x.id];
       const int32_t* b = c.rk.data() + g.eptr[y.id];
@@ -395,7 +503,9 @@ void canonicalise(const GraphIn& g, const std::vector<int64_t>& deg, Canon& c) {
         if (a[j] != b[j]) return a[j] < b[j];
       return x.id < y.id;
     });
-    for (size_t t = 0; t < ids.size(); ++t) ids[t] = keys[t].id;
+    parallel_chunks(static_cast<int64_t>(ids.size()), [&](int, int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t) ids[t] = keys[t].id;
+    });
   }
 }
 
@@ -408,24 +518,44 @@ double blowup_norm2(const GraphIn& g, const Canon& c) {
   S[0][0] = 1.0L;
   for (int a = 1; a <= g.r; ++a)
     for (int b = 1; b <= a; ++b) S[a][b] = (long double)b * S[a - 1][b] + S[a - 1][b - 1];
+  // groups of equal vertex sets are summed in blocks of a fixed number of
+  // edges (a block starts at the first group beginning in it), the block
+  // sums added in order: the value does not depend on the thread count
+  constexpr int64_t kBlk = 1 << 16;
   long double tot = 0.0L, fact = 1.0L;
   for (int k = 1; k <= g.r; ++k) {
     fact *= (long double)k;
     const long double beta = fact * S[g.r][k];
     const auto& ids = c.order[k];
-    size_t t = 0;
-    while (t < ids.size()) {
-      long double W = 0.0L;
-      size_t u = t;
-      for (; u < ids.size(); ++u) {
-        if (u > t && !std::equal(c.rk.data() + g.eptr[ids[u]], c.rk.data() + g.eptr[ids[u]] + k,
-                                 c.rk.data() + g.eptr[ids[t]]))
-          break;
-        W += g.w != nullptr ? (long double)g.w[ids[u]] : (long double)k;
+    const int64_t ne = static_cast<int64_t>(ids.size());
+    auto same = [&](int64_t a, int64_t b) {
+      return std::equal(c.rk.data() + g.eptr[ids[a]], c.rk.data() + g.eptr[ids[a]] + k, c.rk.data() + g.eptr[ids[b]]);
+    };
+    auto group_start = [&](int64_t t) {   // first group that begins at or after t
+      while (t > 0 && t < ne && same(t, t - 1)) ++t;
+      return t;
+    };
+    const int64_t nb = (ne + kBlk - 1) / kBlk;
+    std::vector<long double> part(nb, 0.0L);
+    parallel_chunks(nb, [&](int, int64_t b0, int64_t b1) {
+      for (int64_t b = b0; b < b1; ++b) {
+        int64_t t = group_start(b * kBlk);
+        const int64_t end = group_start(std::min(ne, (b + 1) * kBlk));
+        long double acc = 0.0L;
+        while (t < end) {
+          long double W = 0.0L;
+          int64_t u = t;
+          for (; u < ne; ++u) {
+            if (u > t && !same(u, t)) break;
+            W += g.w != nullptr ? (long double)g.w[ids[u]] : (long double)k;
+          }
+          acc += W * W / beta;
+          t = u;
+        }
+        part[b] = acc;
       }
-      tot += W * W / beta;
-      t = u;
-    }
+    }, 1);
+    for (int64_t b = 0; b < nb; ++b) tot += part[b];
   }
   return static_cast<double>(tot);
 }
@@ -668,11 +798,74 @@ int assign_places(Plan& P) {
     }
   }
   std::vector<int32_t> glist(nnz);
-  for (int64_t q = 0; q < nnz; ++q) glist[q] = loc[P.tslot[q]];
+  parallel_chunks(nnz, [&](int, int64_t q0, int64_t q1) {
+    for (int64_t q = q0; q < q1; ++q) glist[q] = loc[P.tslot[q]];
+  });
   if (nnz > 0 && hipMemcpy(P.d_loc, loc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice) != hipSuccess)
     return STTSV_EHIP;
   P.glist = std::move(glist);
   return stage_level0(P);
+}
+
+// Node-major incidence lists: for every vertex u, the slots holding u in
+// canonical edge order (a vertex occurs once per edge).  Counting sort by
+// vertex over the canonical edges, in chunks of consecutive edges: per-chunk
+// counts, per-vertex offsets chunk by chunk, then each chunk scatters its
+// slots in edge order -- the lists a sequential pass would make.
+static void build_node_major(Plan& P, int32_t n) {
+  const int64_t m = P.m;
+  const int T = std::min(8, chunk_count(m, 1 << 16));
+  std::vector<int64_t> cut(T + 1);
+  for (int t = 0; t <= T; ++t) cut[t] = m * t / T;
+  // first bucket of every chunk (buckets are in canonical edge order)
+  auto bucket_of = [&](int64_t cidx) {
+    size_t lo = 0, hi = P.buckets.size();
+    while (hi - lo > 1) {
+      const size_t mid = (lo + hi) / 2;
+      if (P.buckets[mid].edge_off <= cidx) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  auto each_slot = [&](int64_t c0, int64_t c1, auto&& f) {
+    size_t b = bucket_of(c0);
+    for (int64_t cidx = c0; cidx < c1; ++cidx) {
+      while (cidx >= P.buckets[b].edge_off + P.buckets[b].m) ++b;
+      const Bucket& B = P.buckets[b];
+      const int64_t i = cidx - B.edge_off;
+      for (int j = 0; j < B.k; ++j) f(B.slot_off + (int64_t)j * B.m + i);
+    }
+  };
+  std::vector<std::vector<int32_t>> cnt(T, std::vector<int32_t>(T > 1 ? (size_t)n : 0, 0));
+  if (T == 1) {
+    std::vector<int64_t> cur(P.tptr.begin(), P.tptr.end() - 1);
+    each_slot(0, m, [&](int64_t s) { P.tslot[cur[P.mem[s]]++] = static_cast<int32_t>(s); });
+    return;
+  }
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] { each_slot(cut[t], cut[t + 1], [&](int64_t s) { cnt[t][P.mem[s]]++; }); });
+    for (auto& x : th) x.join();
+  }
+  parallel_chunks(n, [&](int, int64_t u0, int64_t u1) {
+    for (int64_t u = u0; u < u1; ++u) {
+      int64_t run = P.tptr[u];
+      for (int t = 0; t < T; ++t) {
+        const int32_t c = cnt[t][u];
+        cnt[t][u] = static_cast<int32_t>(run - P.tptr[u]);   // offset inside u's list
+        run += c;
+      }
+    }
+  });
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&, t] {
+      each_slot(cut[t], cut[t + 1], [&](int64_t s) {
+        const int32_t u = P.mem[s];
+        P.tslot[P.tptr[u] + cnt[t][u]++] = static_cast<int32_t>(s);
+      });
+    });
+  for (auto& x : th) x.join();
 }
 
 int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
@@ -787,9 +980,15 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
   std::vector<std::vector<long double>> utab(rmax + 1);
   std::vector<std::vector<double>> dtab(rmax + 1);
   if (weighted) wgt.assign(m, 0.0);
-  {
-    std::vector<int64_t> cur(P->tptr.begin(), P->tptr.end() - 1);
+  if (weighted)
     for (int g = 0; g < G; ++g) {
+      if (gs[g].w == nullptr && dtab[gs[g].r].empty()) dtab[gs[g].r] = weight_table(gs[g].r);
+      if (gs[g].w != nullptr && utab[gs[g].r].empty()) utab[gs[g].r] = unit_weight_table(gs[g].r);
+    }
+  {
+    // graphs of a batch in parallel (each writes its own edges, slots and
+    // vertices); inside a graph the loops are parallel again
+    auto one_graph = [&](int g) {
       const GraphIn& in = gs[g];
       const GraphInfo& I = P->graphs[g];
       Canon c;
@@ -800,33 +999,35 @@ int build_plan(int G, const GraphIn* gs, const sttsv_opts* opts, Plan** out) {
         if (ids.empty()) continue;
         const Bucket& B = P->buckets[bidx[in.r][k][gmode[g][k]]];
         const int64_t base = goff[g][k];
-        for (size_t t = 0; t < ids.size(); ++t) {
-          const int64_t e = ids[t];
-          const int64_t i = base + (int64_t)t;                  // edge index in the bucket
-          P->perm[B.edge_off + i] = I.eoff + e;
-          if (G > 1) gid[B.edge_off + i] = g;
-          if (weighted) {
-            if (in.w == nullptr) {
-              if (dtab[in.r].empty()) dtab[in.r] = weight_table(in.r);
-              wgt[B.edge_off + i] = dtab[in.r][k];
-            } else {
-              if (utab[in.r].empty()) utab[in.r] = unit_weight_table(in.r);
-              wgt[B.edge_off + i] = static_cast<double>((long double)in.w[e] * utab[in.r][k]);
+        parallel_chunks(static_cast<int64_t>(ids.size()), [&](int, int64_t t0, int64_t t1) {
+          for (int64_t t = t0; t < t1; ++t) {
+            const int64_t e = ids[t];
+            const int64_t i = base + t;                           // edge index in the bucket
+            P->perm[B.edge_off + i] = I.eoff + e;
+            if (G > 1) gid[B.edge_off + i] = g;
+            if (weighted)
+              wgt[B.edge_off + i] = in.w == nullptr ? dtab[in.r][k]
+                                                    : static_cast<double>((long double)in.w[e] * utab[in.r][k]);
+            const int32_t* a = c.rk.data() + in.eptr[e];
+            for (int j = 0; j < k; ++j) {
+              const int64_t s = B.slot_off + (int64_t)j * B.m + i;
+              P->mem[s] = I.voff + c.inv_rank[a[j]];
+              memr[s] = I.voff + a[j];
             }
           }
-          const int32_t* a = c.rk.data() + in.eptr[e];
-          for (int j = 0; j < k; ++j) {
-            const int32_t u = I.voff + c.inv_rank[a[j]];
-            const int64_t s = B.slot_off + (int64_t)j * B.m + i;
-            P->mem[s] = u;
-            memr[s] = I.voff + a[j];
-            P->tslot[cur[u]++] = static_cast<int32_t>(s);
-          }
-        }
+        });
       }
       P->graphs[g].connected = connected_graph(in, degs[g]);
       P->graphs[g].norm2 = blowup_norm2(in, c);
+    };
+    if (G == 1) {
+      one_graph(0);
+    } else {
+      parallel_chunks(G, [&](int, int64_t g0, int64_t g1) {
+        for (int64_t g = g0; g < g1; ++g) one_graph(static_cast<int>(g));
+      }, 1);
     }
+    build_node_major(*P, n);
   }
   P->connected = true;
   for (const GraphInfo& I : P->graphs) P->connected = P->connected && I.connected;

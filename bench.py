@@ -68,7 +68,7 @@ GEN_LO = [1, 9, 17, 25, 33, 41, 49, 57]
 GEN_HI = [8, 16, 24, 32, 40, 48, 56, 63]
 
 
-def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64"):
+def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64", bucket_s=None):
     """Algorithmic FLOPs and HBM bytes of every stage.  Edge stages: series
     FMAs x 2 and 20 B per incidence (member id, gathered x, contribution);
     fused generic stages: the same summed over the buckets that no per-bucket
@@ -78,34 +78,50 @@ def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64"):
     level 0), per chunk its 12 B descriptor and the 8 B result.  An FP32
     apply runs compact: 12 B per incidence (4 B id, FP32 x, 32-bit
     contribution), 4 B more per vertex for the FP32 copy of x, and 4 B per
-    level-0 term read."""
+    level-0 term read.  Fused launches (kinds 1, 5: one-lane generic kernel with
+    its suffix stacks in LDS / in global memory; 4: lane groups) cover the
+    buckets that no per-bucket stage covers, whose window is in the stage's
+    range and whose kernel and stack placement match (bucket_s: the plan's
+    stack flags).  Each entry: (FLOPs, bytes, description, launch threads or
+    None)."""
     compact = prec == "fp32"
+    sbit = 1 if prec == "fp64" else 2
     inc_b = 12.0 if compact else 20.0
     per_bucket = {s["size"] for s in stages if s["kind"] == 0}
     if bucket_l is None:
         bucket_l = [0] * len(bucket_k)
     out = []
+    def kind_of(lanes, stack):
+        if lanes > 0:
+            return 4
+        return 1 if bucket_s is None or stack & sbit else 5
     for s in stages:
         if s["kind"] == 0:
             k, m = s["size"], s["count"]
-            out.append((2.0 * edge_fma(k, r) * m, inc_b * k * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m)))
-        elif s["kind"] in (1, 4):
+            out.append((2.0 * edge_fma(k, r) * m, inc_b * k * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m),
+                        None))
+        elif s["kind"] in (1, 4, 5):
             g = s["size"]
             f = b = 0.0
-            for k, m, lanes in zip(bucket_k, bucket_m, bucket_l):
+            threads = 0
+            stacks = bucket_s if bucket_s is not None else [0] * len(bucket_k)
+            for k, m, lanes, st_ in zip(bucket_k, bucket_m, bucket_l, stacks):
                 W = r - k + 1
                 if (k >= 4 and k not in per_bucket and GEN_LO[g] <= W <= GEN_HI[g]
-                        and (lanes > 0) == (s["kind"] == 4)):
+                        and kind_of(lanes, st_) == s["kind"]):
                     f += 2.0 * edge_fma(k, r) * m
                     b += inc_b * k * m
-            what = "generic" if s["kind"] == 1 else "lane-group"
-            out.append((f, b, "%s edges W in [%d,%d], %d edges" % (what, GEN_LO[g], GEN_HI[g], s["count"])))
+                    threads += 64 * ((m + 63) // 64) if lanes == 0 else 256 * ((m * lanes + 255) // 256)
+            what = {1: "generic", 5: "generic (global-memory stacks)", 4: "lane-group"}[s["kind"]]
+            out.append((f, b, "%s edges W in [%d,%d], %d edges" % (what, GEN_LO[g], GEN_HI[g], s["count"]),
+                        threads))
         elif s["kind"] == 3:
-            out.append((0.0, (24.0 if compact else 20.0) * s["count"], "x into degree-rank order, n=%d" % s["count"]))
+            out.append((0.0, (24.0 if compact else 20.0) * s["count"], "x into degree-rank order, n=%d" % s["count"],
+                        None))
         else:
             per_term = (6.0 if compact else 10.0) if s["size"] == 0 else 8.0
             out.append((0.0, per_term * s["in_len"] + 20.0 * s["count"],
-                        "reduce level %d, %d chunks" % (s["size"], s["count"])))
+                        "reduce level %d, %d chunks" % (s["size"], s["count"]), None))
     return out
 
 
@@ -181,7 +197,7 @@ def measured_valu(kernel, grid, workload="zipf"):
 SMALL_KIND = {2: 0, 3: 1, 4: 2, 5: 3, 6: 4, 7: 5}
 
 
-def stage_kernel(s, prec, r):
+def stage_kernel(s, prec, r, threads=None):
     """Kernel name (template form, as the profiler prints it) and grid size
     of a stage; grid None where one launch per apply has that name.  FP32
     applies run the compact variants (template flag true; the workloads with
@@ -190,10 +206,10 @@ def stage_kernel(s, prec, r):
     if s["kind"] == 0 and s["size"] in SMALL_KIND:
         return ("edge_small<%s, %d, %d, %s>" % (t, r - s["size"] + 1, SMALL_KIND[s["size"]], cp),
                 (s["count"] + 255) // 256 * 256)
-    if s["kind"] == 1:
-        return "edge_generic<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), None
+    if s["kind"] in (1, 5):   # two launches of one range share the name: the grid tells them apart
+        return "edge_generic<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), threads
     if s["kind"] == 4:
-        return "edge_coop<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), None
+        return "edge_coop<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), threads
     if s["kind"] == 2:
         if s["size"] == 0:
             return "reduce_level0<%s>" % ("double" if prec == "fp64" else "unsigned int"), None
@@ -209,9 +225,9 @@ def roofline_of(stages, work, prec, r, workload=None):
     the dominant kernel."""
     i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
     t = stages[i]["ms"] * 1e-3
-    flops, byts, name = work[i]
+    flops, byts, name, threads = work[i]
     peak_f = PEAK_FP64_VALU      # FP64 FMA and non-packed FP32 FMA issue at the same rate
-    kname, grid = stage_kernel(stages[i], prec, r)
+    kname, grid = stage_kernel(stages[i], prec, r, threads)
     traffic = measured_traffic(kname, grid, workload) if kname and workload else None
     if flops / peak_f >= byts / PEAK_HBM:
         roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_f / 1e12, unit="TFLOP/s",
@@ -322,6 +338,7 @@ def _stage_rooflines(plan, xd, yd, r, nnz, reps, workload=None):
     from paper_2311_08595_amd import _lib as L
     bk, bm = plan.query(L.Q_BUCKET_K).tolist(), plan.query(L.Q_BUCKET_M).tolist()
     bl = plan.query(L.Q_BUCKET_LANES).tolist()
+    bs = plan.query(L.Q_BUCKET_STACK).tolist()
     out = {}
     for prec in ("fp64", "fp32"):
         stages = stage_table(plan, xd, yd, prec, reps)
@@ -330,7 +347,7 @@ def _stage_rooflines(plan, xd, yd, r, nnz, reps, workload=None):
             if st_["kind"] == 2:
                 st_["in_len"] = prev
                 prev = st_["count"]
-        work = stage_work(stages, bk, bm, r, bl, prec)
+        work = stage_work(stages, bk, bm, r, bl, prec, bs)
         best, roof = roofline_of(stages, work, prec, r, workload)
         roof["avg_kernel_ms"] = best["ms"]
         roof["stages_ms_sum"] = sum(s_["ms"] for s_ in stages)
@@ -478,6 +495,7 @@ def profile_apply(a):
         del src, dst
         log("[profile] %s: set-up done, %d MiB marker copy" % (w["name"], mib))
         bk, bm, bl = p.query(L.Q_BUCKET_K), p.query(L.Q_BUCKET_M), p.query(L.Q_BUCKET_LANES)
+        bs = p.query(L.Q_BUCKET_STACK)
         for prec in ("fp64", "fp32"):
             for _ in range(a.steps):
                 p.apply(xd, yd, precision=prec)
@@ -488,9 +506,9 @@ def profile_apply(a):
                 if st_["kind"] == 2:
                     st_["in_len"] = prev
                     prev = st_["count"]
-            work = stage_work(stages, bk, bm, w["r"], bl, prec)
+            work = stage_work(stages, bk, bm, w["r"], bl, prec, bs)
             i = max(range(len(stages)), key=lambda j: stages[j]["ms"])
-            kname, grid = stage_kernel(stages[i], prec, w["r"])
+            kname, grid = stage_kernel(stages[i], prec, w["r"], work[i][3])
             log("[profile] %s %s: %d applies, %d stage-timed passes; dominant stage %s (kernel %s, grid %s): "
                 "%.2f us by HIP events, %.4g FLOP, %.4g B algorithmic"
                 % (w["name"], prec, a.steps, a.stage_reps, work[i][2], kname, grid, stages[i]["ms"] * 1e3,
@@ -802,7 +820,7 @@ def main():
         tune_s = time.perf_counter() - t0
         log("[bench] autotuned in %.2f s" % tune_s)
     res = {"bucket_k": plan.query(L.Q_BUCKET_K).tolist(), "bucket_m": plan.query(L.Q_BUCKET_M).tolist(),
-           "bucket_l": plan.query(L.Q_BUCKET_LANES).tolist()}
+           "bucket_l": plan.query(L.Q_BUCKET_LANES).tolist(), "bucket_s": plan.query(L.Q_BUCKET_STACK).tolist()}
     for prec in ("fp64", "fp32"):
         log("[bench] timing STTSV %s" % prec)
         dt = time_apply(prec) if tune_s is not None else untuned[prec]
@@ -846,7 +864,7 @@ def main():
     from paper_2311_08595_amd import _lib
     bk, bm = res["bucket_k"], res["bucket_m"]
     for prec in ("fp64", "fp32"):
-        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r, res["bucket_l"], prec)
+        res[prec]["work"] = stage_work(res[prec]["stages"], bk, bm, r, res["bucket_l"], prec, res["bucket_s"])
     best, roof = roofline_of(res["fp64"]["stages"], res["fp64"]["work"], "fp64", r, "zipf")
     roof["avg_kernel_ms"] = best["ms"]
     out["roofline"] = roof

@@ -261,6 +261,7 @@ class Plan:
                  _lib.Q_BUCKET_M: inf["nbuckets"], _lib.Q_TPTR: inf["n"] + 1,
                  _lib.Q_TSLOT: inf["nnz"], _lib.Q_BUCKET_R: inf["nbuckets"],
                  _lib.Q_BUCKET_RUNS: inf["nbuckets"], _lib.Q_BUCKET_LANES: inf["nbuckets"],
+                 _lib.Q_BUCKET_STACK: inf["nbuckets"],
                  _lib.Q_CONTRIB: inf["nnz"]}
         if what in (_lib.Q_WEIGHTS, _lib.Q_SCALE_EXP):
             sizes[what] = self.graph_info(0)["r"] + 1

@@ -31,7 +31,7 @@ PREC = {"fp64": 0, "fp32": 1}
 SCHEDULE = {"fp64": 0, "fp32_fp64": 1}
 
 Q_PERM, Q_MEM, Q_BUCKET_K, Q_BUCKET_M, Q_TPTR, Q_TSLOT, Q_WEIGHTS, Q_SCALE_EXP, Q_BUCKET_R, Q_BUCKET_RUNS, \
-    Q_CONTRIB, Q_BUCKET_LANES, Q_CCSS_LEVEL_N, Q_CCSS_VERT, Q_CCSS_PARENT, Q_CCSS_LEAF = range(16)
+    Q_CONTRIB, Q_BUCKET_LANES, Q_CCSS_LEVEL_N, Q_CCSS_VERT, Q_CCSS_PARENT, Q_CCSS_LEAF, Q_BUCKET_STACK = range(17)
 
 # every symbol the header declares
 EXPORTS = ["sttsv_plan", "sttsv_apply", "sttsv_apply_prec", "sttsv_apply_timed", "sttsv_apply_naive",

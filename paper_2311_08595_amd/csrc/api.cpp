@@ -258,6 +258,18 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
         return copy_out<int64_t, int64_t>(p.tptr, out, count);
       case STTSV_Q_TSLOT:
         return copy_out<int32_t, int64_t>(p.tslot, out, count);
+      case STTSV_Q_BUCKET_STACK: {
+        std::vector<int64_t> v;
+        for (const auto& b : p.buckets) {
+          int64_t f = 0;
+          for (int t = 0; t < 2; ++t) {
+            const bool generic = b.k >= 4 && b.small_kind[t] < 0 && b.coop[t] == 0;
+            if (generic && b.desc[t].lds_stack) f |= (1 << t);
+          }
+          v.push_back(f);
+        }
+        return copy_out<int64_t, int64_t>(v, out, count);
+      }
       case STTSV_Q_BUCKET_K:
       case STTSV_Q_BUCKET_M:
       case STTSV_Q_BUCKET_R:

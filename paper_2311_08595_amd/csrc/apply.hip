@@ -392,7 +392,10 @@ void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t*
     *size = p.buckets[S.index].k;
     *count = p.buckets[S.index].m;
   } else if (S.type == 1) {
-    if (p.groups[S.index].coop) *kind = 4;
+    if (p.groups[S.index].coop)
+      *kind = 4;
+    else if (p.groups[S.index].lds == 0)
+      *kind = 5;                                 // generic kernel, suffix stacks in global memory
     *size = p.groups[S.index].range;
     int64_t m = 0;
     for (int b : p.groups[S.index].buckets) m += p.buckets[b].m;

@@ -656,39 +656,59 @@ int build_groups(Plan& P) {
           return wa > wb;
         });
         const size_t tsz = t == 0 ? sizeof(double) : sizeof(float);
-        std::vector<BucketDesc> bks;
-        std::vector<GenTask> tasks;
-        for (size_t q = 0; q < grp.buckets.size(); ++q) {
-          Bucket& B = P.buckets[grp.buckets[q]];
-          if (seq == 0 && t == 0) B.task0 = static_cast<int64_t>(tasks.size());
-          const int W = B.r - B.k + 1;
-          const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, static_cast<int>(tsz));
-          BucketDesc& d = B.desc[t];
-          const bool use_lds = B.lds_pref[t] >= 0 ? B.lds_pref[t] == 1 && need <= kLdsMax : need <= kLdsBudget;
-          if (use_lds) {
-            d.lds_stack = 1;
-            grp.lds = std::max(grp.lds, static_cast<size_t>(need));
-          } else {
-            d.lds_stack = 0;
-            if (B.gstack[t] == nullptr) {
-              const size_t bytes = (size_t)kg_stack_bytes(B.k, W, static_cast<int>(tsz)) * (size_t)B.m;
-              if (hipMalloc(&B.gstack[t], bytes) != hipSuccess) return STTSV_ENOMEM;
-              P.device_bytes += (int64_t)bytes;
+        auto need_of = [&](const Bucket& B) {
+          return (int64_t)kGenBlock * kg_stack_bytes(B.k, B.r - B.k + 1, static_cast<int>(tsz));
+        };
+        auto lds_of = [&](const Bucket& B) {
+          const int64_t need = need_of(B);
+          return B.lds_pref[t] >= 0 ? B.lds_pref[t] == 1 && need <= kLdsMax : need <= kLdsBudget;
+        };
+        // a launch reserves its largest LDS stack for every block, so buckets
+        // whose stacks live in global memory get a launch of their own (else
+        // they would run at the LDS-limited occupancy of the others)
+        std::vector<int> in_lds, in_glb;
+        for (int b : grp.buckets) (lds_of(P.buckets[b]) ? in_lds : in_glb).push_back(b);
+        for (int part = 0; part < 2; ++part) {
+          const std::vector<int>& list = part == 0 ? in_lds : in_glb;
+          if (list.empty()) continue;
+          GenGroup sub;
+          sub.range = grp.range;
+          sub.seq = grp.seq;
+          sub.f64 = grp.f64;
+          sub.coop = false;
+          sub.buckets = list;
+          std::vector<BucketDesc> bks;
+          std::vector<GenTask> tasks;
+          for (size_t q = 0; q < sub.buckets.size(); ++q) {
+            Bucket& B = P.buckets[sub.buckets[q]];
+            if (seq == 0 && t == 0) B.task0 = static_cast<int64_t>(tasks.size());
+            const int W = B.r - B.k + 1;
+            BucketDesc& d = B.desc[t];
+            if (part == 0) {
+              d.lds_stack = 1;
+              sub.lds = std::max(sub.lds, static_cast<size_t>(need_of(B)));
+            } else {
+              d.lds_stack = 0;
+              if (B.gstack[t] == nullptr) {
+                const size_t bytes = (size_t)kg_stack_bytes(B.k, W, static_cast<int>(tsz)) * (size_t)B.m;
+                if (hipMalloc(&B.gstack[t], bytes) != hipSuccess) return STTSV_ENOMEM;
+                P.device_bytes += (int64_t)bytes;
+              }
+              d.gstack = B.gstack[t];
             }
-            d.gstack = B.gstack[t];
+            bks.push_back(d);
+            const int64_t nblk = (B.m + kGenBlock - 1) / kGenBlock;
+            for (int64_t blk = 0; blk < nblk; ++blk)
+              tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
           }
-          bks.push_back(d);
-          const int64_t nblk = (B.m + kGenBlock - 1) / kGenBlock;
-          for (int64_t blk = 0; blk < nblk; ++blk)
-            tasks.push_back(GenTask{static_cast<int32_t>(q), static_cast<int32_t>(blk)});
+          sub.ntasks = (int64_t)tasks.size();
+          P.groups.push_back(std::move(sub));
+          GenGroup& H = P.groups.back();
+          const int64_t before = P.device_bytes;
+          if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P.device_bytes)) != STTSV_OK) return rc;
+          if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P.device_bytes)) != STTSV_OK) return rc;
+          H.bytes = P.device_bytes - before;
         }
-        grp.ntasks = (int64_t)tasks.size();
-        P.groups.push_back(std::move(grp));
-        GenGroup& H = P.groups.back();
-        const int64_t before = P.device_bytes;
-        if ((rc = upload(&H.d_bks, bks.data(), bks.size(), &P.device_bytes)) != STTSV_OK) return rc;
-        if ((rc = upload(&H.d_tasks, tasks.data(), tasks.size(), &P.device_bytes)) != STTSV_OK) return rc;
-        H.bytes = P.device_bytes - before;
        }
       }
     }

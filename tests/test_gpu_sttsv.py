@@ -396,3 +396,32 @@ def test_compact_fp32_contributions_are_words(torch_cuda):
     nz = c64 != 0
     assert np.max(np.abs(c32[nz] - c64[nz]) / np.abs(c64[nz])) <= 1e-5
     assert not np.array_equal(c32, c64)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_list_covers_every_edge_once(torch_cuda, prec):
+    """The launch sequence of an apply (per-bucket kernels, fused generic
+    launches with LDS or global-memory stacks, lane-group launches) processes
+    every edge exactly once, and the stack flags agree with the fused
+    launches' kinds."""
+    import ctypes
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    w = wl.heavy_tail(seed=21, n=20000, m=200000)
+    lib = _lib.load()
+    with st.Plan(w["eptr"], w["eidx"], w["n"], w["r"]) as plan:
+        xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+        yd = torch.empty_like(xd)
+        cap = 256
+        ns = ctypes.c_int32()
+        kinds, sizes = (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)()
+        counts, ms = (ctypes.c_int64 * cap)(), (ctypes.c_float * cap)()
+        _lib.check(lib.sttsv_apply_timed(plan._h, ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(yd.data_ptr()),
+                                         _lib.PREC[prec], cap, ctypes.byref(ns), kinds, sizes, counts, ms))
+        stacks = plan.query(_lib.Q_BUCKET_STACK)
+        m = len(w["eptr"]) - 1
+        edge_stages = [(kinds[i], counts[i]) for i in range(ns.value) if kinds[i] in (0, 1, 4, 5)]
+    assert sum(c for _, c in edge_stages) == m
+    assert set(int(s) for s in stacks) <= {0, 1, 2, 3}
+    _say(f"  {prec}: stage kinds {sorted(set(k for k, _ in edge_stages))}")

@@ -304,8 +304,11 @@ int init_lanes(Plan& p) {
 // Edge stages of np precisions (precs[i] with per-graph skip flags skips[i])
 // inside one fork/join of the stream lanes.
 // x32 (nullable): the FP32 stages run compact, gathering from it.
+// gates[i] (nullable): per-stage flags of precision i, used as the stage's
+// done flag.
 static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, const int32_t* const* skips, int np,
-                                   const int32_t* done, hipStream_t s, XOrder order, const float* x32) {
+                                   const int32_t* done, hipStream_t s, XOrder order, const float* x32,
+                                   const int32_t* const* gates) {
   const double* xr = order == XOrder::kRank ? x : p.d_xr;
   const bool multi = !(p.flags & STTSV_FLAG_ONE_STREAM) && p.ev_fork != nullptr;
   int nl = 1;
@@ -322,10 +325,13 @@ static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, c
   for (int i = 0; i < np && e == hipSuccess; ++i) {
     const int seq = precs[i] == STTSV_PREC_FP32 ? 1 : 0;
     const bool lanes = nl > 1 && p.lanes[seq] > 1;
-    const EdgeCall c = edge_call(p, xr, done, skips[i], precs[i] == STTSV_PREC_FP32 ? x32 : nullptr);
-    for (const Stage& S : p.stages[seq]) {
+    EdgeCall c = edge_call(p, xr, done, skips[i], precs[i] == STTSV_PREC_FP32 ? x32 : nullptr);
+    const int32_t* gate = gates != nullptr ? gates[i] : nullptr;
+    for (size_t si = 0; si < p.stages[seq].size(); ++si) {
+      const Stage& S = p.stages[seq][si];
       if (S.type == 2 || S.type == 3) continue;
       const hipStream_t ls = lanes && S.lane > 0 ? p.aux[S.lane - 1] : s;
+      if (gate != nullptr) c.done = gate + si;
       if ((e = launch_stage_call(p, S, c, nullptr, ls)) != hipSuccess) break;
     }
   }
@@ -345,21 +351,23 @@ static hipError_t launch_edge_sets(Plan& p, const double* x, const int* precs, c
 }
 
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s, XOrder order, bool compact) {
+                        hipStream_t s, XOrder order, bool compact, const int32_t* gate) {
   // a compact launch needs the FP32 copy of x, which only the permute makes
   if (compact && (precision != STTSV_PREC_FP32 || order != XOrder::kVertex || !p.compact_ok))
     return hipErrorInvalidValue;
   p.contrib_compact = compact;
-  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order, compact ? p.d_xr32 : nullptr);
+  return launch_edge_sets(p, x, &precision, &gskip, 1, done, s, order, compact ? p.d_xr32 : nullptr, &gate);
 }
 
 hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
-                             const int32_t* skip64, hipStream_t s, const float* x32) {
+                             const int32_t* skip64, hipStream_t s, const float* x32, const int32_t* gate32,
+                             const int32_t* gate64) {
   const int precs[2] = {STTSV_PREC_FP32, STTSV_PREC_FP64};
   const int32_t* skips[2] = {skip32, skip64};
+  const int32_t* gates[2] = {gate32, gate64};
   if (x32 != nullptr && !p.compact_ok) return hipErrorInvalidValue;
   p.contrib_compact = false;
-  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank, x32);
+  return launch_edge_sets(p, x, precs, skips, 2, done, s, XOrder::kRank, x32, gates);
 }
 
 hipError_t launch_reduction_phased(Plan& p, double* y, const int32_t* phase32, const int32_t* done, hipStream_t s,

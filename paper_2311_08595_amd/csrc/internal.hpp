@@ -325,8 +325,12 @@ int set_reuse(Plan& p, Bucket& b, bool by_flag);   // prefix-reuse runs of a buc
 // x order of an edge launch: the caller's vertex order (copied into rank
 // order first), already in rank order, or copied by an earlier launch.
 enum class XOrder { kVertex, kRank, kCopied };
+// gate (nullable): one flag per edge stage of the precision's sequence
+// (indexed as the plan's stage list); a stage's kernels leave at once when
+// its flag is set, in place of done.
 hipError_t launch_edges(Plan& p, const double* x, int precision, const int32_t* done, const int32_t* gskip,
-                        hipStream_t s, XOrder order = XOrder::kVertex, bool compact = false);
+                        hipStream_t s, XOrder order = XOrder::kVertex, bool compact = false,
+                        const int32_t* gate = nullptr);
 // rank_out: write y in degree-rank order instead of vertex order.
 hipError_t launch_reduction(Plan& p, double* y, const int32_t* done, hipStream_t s, bool rank_out = false,
                             bool compact = false);
@@ -340,7 +344,8 @@ hipError_t launch_reduction_phased(Plan& p, double* y, const int32_t* phase32, c
 // schedule, where each graph runs one of the two per iteration.  With x32
 // (the iterate in rank order, rounded to FP32) the FP32 stages run compact.
 hipError_t launch_edges_both(Plan& p, const double* x, const int32_t* done, const int32_t* skip32,
-                             const int32_t* skip64, hipStream_t s, const float* x32);
+                             const int32_t* skip64, hipStream_t s, const float* x32,
+                             const int32_t* gate32 = nullptr, const int32_t* gate64 = nullptr);
 
 // x into degree-rank order (the copy the edge kernels gather from)
 hipError_t launch_permute_x(Plan& p, const double* x, hipStream_t s);

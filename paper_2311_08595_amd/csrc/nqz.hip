@@ -61,6 +61,15 @@ struct Solver {
   int32_t* gn = nullptr;      // vertices of each graph
   int32_t* skip64 = nullptr;  // graph skips the FP64-series edge launches
   int32_t* skip32 = nullptr;  // graph skips the FP32-series edge launches
+  // Batched plans: per edge stage (slot q = sequence * gate_stride + stage
+  // index; sequence 0 = FP64 apply, 1 = FP32-series apply) the graphs whose
+  // edges it may process, gate_graph[gate_ptr[q] .. gate_ptr[q + 1]), and
+  // gate[q] = 1 when none of them runs that sequence in the next iteration:
+  // the stage's kernels then leave at once instead of testing every edge.
+  int32_t* gate = nullptr;
+  int32_t* gate_ptr = nullptr;
+  int32_t* gate_graph = nullptr;
+  int32_t gate_stride = 0, ngate = 0;
   GCtrl* ctrl = nullptr;
   SCtrl* sctrl = nullptr;
   GCtrl* hctrl = nullptr;     // pinned host mirrors
@@ -295,9 +304,21 @@ __global__ void __launch_bounds__(kRedBlock) nqz_final(Solver S) {
   }
 }
 
-// all_done = every graph done (single block)
+// Block 0: all_done = every graph done, no32 = no open graph runs FP32
+// series.  Block 1 + q: the gate of edge stage slot q (a done graph skips
+// both sequences, so all_done closes every gate).
 __global__ void __launch_bounds__(kRedBlock) all_done_check(Solver S) {
   __shared__ double sh[kRedBlock];
+  if (blockIdx.x > 0) {
+    const int q = static_cast<int>(blockIdx.x) - 1;
+    const int32_t* skip = q < S.gate_stride ? S.skip64 : S.skip32;
+    double run = 0.0;
+    for (int t = S.gate_ptr[q] + static_cast<int>(threadIdx.x); t < S.gate_ptr[q + 1]; t += kRedBlock)
+      run = fmax(run, skip[S.gate_graph[t]] ? 0.0 : 1.0);
+    run = block_reduce(run, sh, OpMax());
+    if (threadIdx.x == 0) S.gate[q] = run > 0.0 ? 0 : 1;
+    return;
+  }
   double open = 0.0, open32 = 0.0;
   for (int g = threadIdx.x; g < S.G; g += kRedBlock) {
     open = fmax(open, S.ctrl[g].done ? 0.0 : 1.0);
@@ -339,10 +360,12 @@ hipError_t enqueue_iteration(Plan& p, Solver& S, int schedule) {
   hipError_t e;
   const int32_t* all_done = &S.sctrl->all_done;
   const bool cmp = compact_mixed(p, schedule);
+  const int32_t* gate64 = S.gate;                                          // null for one graph
+  const int32_t* gate32 = S.gate != nullptr ? S.gate + S.gate_stride : nullptr;
   if (schedule == STTSV_SOLVE_FP32_FP64)
-    e = launch_edges_both(p, S.x, all_done, S.skip32, S.skip64, S.s, cmp ? S.x32 : nullptr);
+    e = launch_edges_both(p, S.x, all_done, S.skip32, S.skip64, S.s, cmp ? S.x32 : nullptr, gate32, gate64);
   else
-    e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s, XOrder::kRank);
+    e = launch_edges(p, S.x, STTSV_PREC_FP64, all_done, S.skip64, S.s, XOrder::kRank, false, gate64);
   if (e != hipSuccess) return e;
   // a graph's level-0 workgroups read words while it runs FP32 series (skip32 == 0)
   e = cmp ? launch_reduction_phased(p, S.z, S.skip32, all_done, S.s, true)
@@ -350,7 +373,7 @@ hipError_t enqueue_iteration(Plan& p, Solver& S, int schedule) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((nqz_stats<true>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<true>), dim3(S.G), dim3(kRedBlock), 0, S.s, S);
-  if (S.G > 1) hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
+  if (S.G > 1) hipLaunchKernelGGL(all_done_check, dim3(1 + S.ngate), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x,
                      cmp ? S.x32 : nullptr);
   return hipGetLastError();
@@ -367,7 +390,8 @@ void free_solver(Plan& p) {
   if (S->exec64) (void)hipGraphExecDestroy(S->exec64);
   for (void* q : {(void*)S->x, (void*)S->x32, (void*)S->z, (void*)S->w, (void*)S->part, (void*)S->sums, (void*)S->bgraph,
                   (void*)S->bsub, (void*)S->gblk0, (void*)S->gnblk, (void*)S->voff, (void*)S->gn,
-                  (void*)S->skip64, (void*)S->skip32, (void*)S->ctrl, (void*)S->sctrl})
+                  (void*)S->skip64, (void*)S->skip32, (void*)S->ctrl, (void*)S->sctrl, (void*)S->gate,
+                  (void*)S->gate_ptr, (void*)S->gate_graph})
     (void)hipFree(q);
   if (S->hctrl) (void)hipHostFree(S->hctrl);
   if (S->hsctrl) (void)hipHostFree(S->hsctrl);
@@ -413,6 +437,40 @@ static int ensure_solver(Plan& p) {
       !up(S->gblk0, gblk0.data(), 4 * G) || !up(S->gnblk, gnblk.data(), 4 * G) || !up(S->voff, voff.data(), 4 * G) ||
       !up(S->gn, gn.data(), 4 * G))
     return STTSV_EHIP;
+  if (G > 1) {
+    // graphs of every edge stage: those of the stage's buckets' order r (a
+    // superset of the graphs with edges there, so a closed gate never skips
+    // an edge that runs)
+    const size_t ns = std::max(p.stages[0].size(), p.stages[1].size());
+    S->gate_stride = static_cast<int32_t>(ns);
+    S->ngate = static_cast<int32_t>(2 * ns);
+    std::vector<int32_t> ptr(1, 0), gl;
+    std::vector<char> in(G);
+    for (int seq = 0; seq < 2; ++seq)
+      for (size_t si = 0; si < ns; ++si) {
+        std::fill(in.begin(), in.end(), 0);
+        if (si < p.stages[seq].size()) {
+          const Stage& st = p.stages[seq][si];
+          std::vector<int> bl;
+          if (st.type == 0)
+            bl.push_back(st.index);
+          else if (st.type == 1)
+            bl = p.groups[st.index].buckets;
+          for (int b : bl)
+            for (int g = 0; g < G; ++g)
+              if (p.graphs[g].r == p.buckets[b].r) in[g] = 1;
+        }
+        for (int g = 0; g < G; ++g)
+          if (in[g]) gl.push_back(g);
+        ptr.push_back(static_cast<int32_t>(gl.size()));
+      }
+    if (gl.empty()) gl.push_back(0);
+    if (!alloc(&S->gate, 4 * std::max<size_t>(1, S->ngate)) || !alloc(&S->gate_ptr, 4 * ptr.size()) ||
+        !alloc(&S->gate_graph, 4 * gl.size()))
+      return STTSV_ENOMEM;
+    if (!up(S->gate_ptr, ptr.data(), 4 * ptr.size()) || !up(S->gate_graph, gl.data(), 4 * gl.size()))
+      return STTSV_EHIP;
+  }
   return STTSV_OK;
 }
 
@@ -470,7 +528,7 @@ int solve(Plan& p, const double* x0, double tol, const sttsv_solve_opts& o, doub
   if ((rc = hip_rc(launch_reduction(p, S.z, nullptr, S.s, true))) != STTSV_OK) return rc;
   hipLaunchKernelGGL((nqz_stats<false>), dim3(S.nblk), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL((nqz_final<false>), dim3(G), dim3(kRedBlock), 0, S.s, S);
-  if (G > 1) hipLaunchKernelGGL(all_done_check, dim3(1), dim3(kRedBlock), 0, S.s, S);
+  if (G > 1) hipLaunchKernelGGL(all_done_check, dim3(1 + S.ngate), dim3(kRedBlock), 0, S.s, S);
   hipLaunchKernelGGL(scale_into, dim3(S.nblk), dim3(kRedBlock), 0, S.s, S, (const double*)S.w, S.x,
                      compact_mixed(p, o.schedule) ? S.x32 : nullptr);
   if (hipGetLastError() != hipSuccess) return STTSV_EHIP;

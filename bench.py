@@ -78,8 +78,9 @@ def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64", bucket
     level 0), per chunk its 12 B descriptor and the 8 B result.  An FP32
     apply runs compact: 12 B per incidence (4 B id, FP32 x, 32-bit
     contribution), 4 B more per vertex for the FP32 copy of x, and 4 B per
-    level-0 term read.  Fused launches (kinds 1, 5: one-lane generic kernel with
-    its suffix stacks in LDS / in global memory; 4: lane groups) cover the
+    level-0 term read.  Fused launches (kinds 1, 5, 6: one-lane generic kernel
+    with its suffix stacks in LDS / in global memory / without stacks, whose
+    extra series products are not counted; 4: lane groups) cover the
     buckets that no per-bucket stage covers, whose window is in the stage's
     range and whose kernel and stack placement match (bucket_s: the plan's
     stack flags).  Each entry: (FLOPs, bytes, description, launch threads or
@@ -94,13 +95,15 @@ def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64", bucket
     def kind_of(lanes, stack):
         if lanes > 0:
             return 4
+        if bucket_s is not None and stack & (sbit << 2):
+            return 6
         return 1 if bucket_s is None or stack & sbit else 5
     for s in stages:
         if s["kind"] == 0:
             k, m = s["size"], s["count"]
             out.append((2.0 * edge_fma(k, r) * m, inc_b * k * m, "edge k=%d (W=%d), %d edges" % (k, r - k + 1, m),
                         None))
-        elif s["kind"] in (1, 4, 5):
+        elif s["kind"] in (1, 4, 5, 6):
             g = s["size"]
             f = b = 0.0
             threads = 0
@@ -112,7 +115,8 @@ def stage_work(stages, bucket_k, bucket_m, r, bucket_l=None, prec="fp64", bucket
                     f += 2.0 * edge_fma(k, r) * m
                     b += inc_b * k * m
                     threads += 64 * ((m + 63) // 64) if lanes == 0 else 256 * ((m * lanes + 255) // 256)
-            what = {1: "generic", 5: "generic (global-memory stacks)", 4: "lane-group"}[s["kind"]]
+            what = {1: "generic", 5: "generic (global-memory stacks)", 6: "generic (no stacks)",
+                    4: "lane-group"}[s["kind"]]
             out.append((f, b, "%s edges W in [%d,%d], %d edges" % (what, GEN_LO[g], GEN_HI[g], s["count"]),
                         threads))
         elif s["kind"] == 3:
@@ -206,7 +210,7 @@ def stage_kernel(s, prec, r, threads=None):
     if s["kind"] == 0 and s["size"] in SMALL_KIND:
         return ("edge_small<%s, %d, %d, %s>" % (t, r - s["size"] + 1, SMALL_KIND[s["size"]], cp),
                 (s["count"] + 255) // 256 * 256)
-    if s["kind"] in (1, 5):   # two launches of one range share the name: the grid tells them apart
+    if s["kind"] in (1, 5, 6):   # launches of one range share the name: the grid tells them apart
         return "edge_generic<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), threads
     if s["kind"] == 4:
         return "edge_coop<%s, %d, %d, %s>" % (t, GEN_LO[s["size"]], GEN_HI[s["size"]], cp), threads

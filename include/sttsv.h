@@ -145,8 +145,9 @@ int sttsv_apply_prec(sttsv_plan_t plan, const double* x, double* y, int32_t prec
  * (kinds[s] = 0, sizes[s] = edge size k, counts[s] = edges in the bucket);
  * a fused launch of the generic kernel over several buckets whose suffix
  * stacks live in LDS (kinds[s] = 1, sizes[s] = window-range index, counts[s]
- * = edges covered) or in global memory (kinds[s] = 5, as for kind 1; see
- * STTSV_Q_BUCKET_STACK); a fused launch
+ * = edges covered), in global memory (kinds[s] = 5, as for kind 1), or that
+ * keeps no suffix stacks and rebuilds each suffix series when it needs it
+ * (kinds[s] = 6, as for kind 1; see STTSV_Q_BUCKET_STACK); a fused launch
  * of the lane-group kernel, where L lanes (a power of two >= |e|) share each
  * edge of buckets with few edges and long series chains (kinds[s] = 4, sizes
  * and counts as for kind 1); one level of
@@ -557,7 +558,10 @@ int sym_cp_descent(sttsv_plan_t plan, int32_t R, double* A, double* lambda, int3
 #define STTSV_Q_BUCKET_STACK 16 /* int64[nb] where each bucket's generic-kernel   */
                                /*            suffix stacks live: bit 0 FP64, bit 1 */
                                /*            FP32 series (1 = LDS, 0 = global    */
-                               /*            memory or no generic kernel)        */
+                               /*            memory or no generic kernel); bit 2 */
+                               /*            FP64, bit 3 FP32: 1 = no stack (the  */
+                               /*            suffix series are recomputed; same  */
+                               /*            bits of y)                          */
 #define STTSV_Q_CCSS_LEVEL_N 12 /* int64[levels] nodes per level of the forest   */
 #define STTSV_Q_CCSS_VERT   13  /* int64[nodes] vertex id of every node, level by  */
                                 /*            level, in node order                 */

@@ -264,7 +264,8 @@ int sttsv_plan_query(sttsv_plan_t plan, int32_t what, void* out, int64_t count) 
           int64_t f = 0;
           for (int t = 0; t < 2; ++t) {
             const bool generic = b.k >= 4 && b.small_kind[t] < 0 && b.coop[t] == 0;
-            if (generic && b.desc[t].lds_stack) f |= (1 << t);
+            if (generic && b.desc[t].lds_stack == 1) f |= (1 << t);
+            if (generic && b.desc[t].lds_stack == sttsv::kStackFree) f |= (4 << t);
           }
           v.push_back(f);
         }

@@ -402,6 +402,8 @@ void stage_desc(const Plan& p, int precision, int stage, int32_t* kind, int32_t*
   } else if (S.type == 1) {
     if (p.groups[S.index].coop)
       *kind = 4;
+    else if (p.groups[S.index].stack_free)
+      *kind = 6;                                 // generic kernel without suffix stacks
     else if (p.groups[S.index].lds == 0)
       *kind = 5;                                 // generic kernel, suffix stacks in global memory
     *size = p.groups[S.index].range;

@@ -51,6 +51,12 @@ constexpr int kg_checkpoint(int W, int tsz) {
 constexpr int64_t kg_stack_bytes(int k, int W, int tsz) {
   return 16LL * k + (int64_t)((k - 3 + kg_checkpoint(W, tsz) - 1) / kg_checkpoint(W, tsz)) * W * tsz;
 }
+// Stack-free generic variant (suffix series recomputed, scalars in LDS):
+// compiled for windows >= kStackFreeMinW only, where a suffix series is
+// long and k = r - W + 1 is small.
+constexpr int kStackFree = 2;
+constexpr int kStackFreeMinW = 9;
+constexpr int64_t kg_scalar_bytes(int k) { return 16LL * k; }
 
 inline int gen_range_of(int W) {
   for (int g = 0; g < kGenRanges; ++g)
@@ -100,7 +106,7 @@ struct BucketDesc {
   int64_t m;            // edges in the bucket
   int32_t k, r, W;      // edge size, tensor order, series window r - k + 1
   int32_t qexp;         // series scale exponent (rho = 2^qexp)
-  int32_t lds_stack;    // generic kernel: 1 = stack in LDS
+  int32_t lds_stack;    // generic kernel: 1 = stack in LDS, 0 = in global memory, kStackFree = none
   int32_t reuse_emin;   // prefix reuse: smallest exponent of z_0, z_1 with an exact rescale
   int32_t lanes;        // lane-group kernel: lanes per edge (power of two >= k, <= 64)
   double wk;            // w(e)/|beta(e)| (r-1)! for w(e) = |e|
@@ -197,6 +203,7 @@ struct Bucket {
 struct GenGroup {
   int range = 0;
   bool coop = false;    // lane-group kernel (else the one-lane generic kernel)
+  bool stack_free = false;   // one-lane generic kernel without suffix stacks
   int seq = 0;          // launch sequence: 0 = FP64 apply, 1 = FP32-series apply
   bool f64 = true;      // series type of the group's kernels
   int64_t ntasks = 0;

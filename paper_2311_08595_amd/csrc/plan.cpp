@@ -659,23 +659,31 @@ int build_groups(Plan& P) {
         auto need_of = [&](const Bucket& B) {
           return (int64_t)kGenBlock * kg_stack_bytes(B.k, B.r - B.k + 1, static_cast<int>(tsz));
         };
-        auto lds_of = [&](const Bucket& B) {
-          const int64_t need = need_of(B);
-          return B.lds_pref[t] >= 0 ? B.lds_pref[t] == 1 && need <= kLdsMax : need <= kLdsBudget;
+        auto free_ok = [&](const Bucket& B) {   // the stack-free variant exists and its scalars fit
+          return B.r - B.k + 1 >= kStackFreeMinW && (int64_t)kGenBlock * kg_scalar_bytes(B.k) <= kLdsMax;
         };
-        // a launch reserves its largest LDS stack for every block, so buckets
-        // whose stacks live in global memory get a launch of their own (else
-        // they would run at the LDS-limited occupancy of the others)
-        std::vector<int> in_lds, in_glb;
-        for (int b : grp.buckets) (lds_of(P.buckets[b]) ? in_lds : in_glb).push_back(b);
-        for (int part = 0; part < 2; ++part) {
-          const std::vector<int>& list = part == 0 ? in_lds : in_glb;
+        // placement: 0 = stack in LDS, 1 = in global memory, 2 = no stack
+        // (tuner choices; without one, LDS when it fits the default budget)
+        auto place_of = [&](const Bucket& B) {
+          const int64_t need = need_of(B);
+          const int pref = B.lds_pref[t];
+          if (pref == kStackFree) return free_ok(B) ? 2 : need <= kLdsBudget ? 0 : 1;
+          return pref >= 0 ? (pref == 1 && need <= kLdsMax ? 0 : 1) : (need <= kLdsBudget ? 0 : 1);
+        };
+        // a launch reserves its largest LDS need for every block, so buckets
+        // of different placements get launches of their own (else global-
+        // stack buckets would run at the LDS-limited occupancy of the others)
+        std::vector<int> parts[3];
+        for (int b : grp.buckets) parts[place_of(P.buckets[b])].push_back(b);
+        for (int part = 0; part < 3; ++part) {
+          const std::vector<int>& list = parts[part];
           if (list.empty()) continue;
           GenGroup sub;
           sub.range = grp.range;
           sub.seq = grp.seq;
           sub.f64 = grp.f64;
           sub.coop = false;
+          sub.stack_free = part == 2;
           sub.buckets = list;
           std::vector<BucketDesc> bks;
           std::vector<GenTask> tasks;
@@ -687,6 +695,9 @@ int build_groups(Plan& P) {
             if (part == 0) {
               d.lds_stack = 1;
               sub.lds = std::max(sub.lds, static_cast<size_t>(need_of(B)));
+            } else if (part == 2) {
+              d.lds_stack = kStackFree;
+              sub.lds = std::max(sub.lds, static_cast<size_t>((int64_t)kGenBlock * kg_scalar_bytes(B.k)));
             } else {
               d.lds_stack = 0;
               if (B.gstack[t] == nullptr) {

@@ -1,7 +1,8 @@
 // Autotuner: picks, per size bucket and series type, among kernel variants
 // that compute bitwise-identical contributions (so tuning never changes y):
 //   * 4 <= k <= 7: register-resident kernel vs the generic kernel;
-//   * generic buckets: suffix stack in LDS vs in global memory;
+//   * generic buckets: suffix stack in LDS vs in global memory vs no stack
+//     (suffix series recomputed; long windows only);
 //   * FP64 register-resident buckets: with or without prefix reuse;
 // and then the stream lane of every edge launch (whole applies timed).
 // Each kernel candidate is launched alone on the plan's stream with the caller's x
@@ -25,7 +26,7 @@ namespace {
 
 struct Choice {
   int use_kr;   // -1 not applicable, 0 generic, 1 register-resident
-  int lds;      // -1 not applicable, 0 global stack, 1 LDS stack
+  int lds;      // -1 not applicable, 0 global stack, 1 LDS stack, kStackFree no stack
   int reuse;    // -1 not applicable, 0 off, 1 prefix reuse
 };
 
@@ -77,17 +78,20 @@ float time_median(F&& launch, int reps, hipStream_t s) {
   return t[t.size() / 2];
 }
 
-// A one-bucket generic launch with the given stack placement.
-float time_generic(Plan& p, Bucket& B, int t, bool lds, const EdgeCall& c, int reps) {
+// A one-bucket generic launch with the given stack placement (0 global,
+// 1 LDS, kStackFree none).
+float time_generic(Plan& p, Bucket& B, int t, int place, const EdgeCall& c, int reps) {
   const EdgeTables& tab = edge_tables();
   const int W = B.r - B.k + 1;
   const int tsz = t == 0 ? 8 : 4;
-  const int64_t need = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, tsz);
-  if (lds && need > kLdsMax) return 1e30f;
+  const int64_t need = place == kStackFree ? (int64_t)kGenBlock * kg_scalar_bytes(B.k)
+                                           : (int64_t)kGenBlock * kg_stack_bytes(B.k, W, tsz);
+  if (place != 0 && need > kLdsMax) return 1e30f;
+  if (place == kStackFree && W < kStackFreeMinW) return 1e30f;
   BucketDesc d = B.desc[t];
   void* tmp = nullptr;
-  d.lds_stack = lds ? 1 : 0;
-  if (!lds) {
+  d.lds_stack = place;
+  if (place == 0) {
     if (B.gstack[t] != nullptr) {
       d.gstack = B.gstack[t];
     } else {
@@ -107,7 +111,7 @@ float time_generic(Plan& p, Bucket& B, int t, bool lds, const EdgeCall& c, int r
       hipMemcpy(d_t, tasks.data(), sizeof(GenTask) * tasks.size(), hipMemcpyHostToDevice) == hipSuccess) {
     const GenLaunchFn fn = t == 0 ? tab.gen64[gen_range_of(W)]
                                   : (c.contrib32 != nullptr ? tab.gen32c : tab.gen32)[gen_range_of(W)];
-    const size_t ldsb = lds ? static_cast<size_t>(need) : 0;
+    const size_t ldsb = place != 0 ? static_cast<size_t>(need) : 0;
     if (fn != nullptr)
       ms = time_median([&] { return fn(c, d_b, d_t, (int64_t)tasks.size(), ldsb, p.stream); }, reps, p.stream);
   }
@@ -192,10 +196,11 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
       const auto& small = t == 0 ? tab.small64 : (c.contrib32 != nullptr ? tab.small32c : tab.small32);
       const SmallLaunchFn kr = (B.k <= 7 && !(p.flags & STTSV_FLAG_GENERIC_ONLY)) ? small[SK_R4 + (B.k - 4)][W] : nullptr;
       if (!cached) {
-        const float g_lds = time_generic(p, B, t, true, c, reps);
-        const float g_glb = time_generic(p, B, t, false, c, reps);
-        const float g_best = std::min(g_lds, g_glb);
-        ch.lds = g_lds <= g_glb ? 1 : 0;
+        const float g_lds = time_generic(p, B, t, 1, c, reps);
+        const float g_glb = time_generic(p, B, t, 0, c, reps);
+        const float g_free = W >= kStackFreeMinW ? time_generic(p, B, t, kStackFree, c, reps) : 1e30f;
+        const float g_best = std::min(g_lds, std::min(g_glb, g_free));
+        ch.lds = g_lds == g_best ? 1 : g_free == g_best ? kStackFree : 0;
         ch.use_kr = -1;
         if (kr != nullptr) {
           const BucketDesc d = B.desc[t];

@@ -376,6 +376,53 @@ def test_autotune_keeps_bits(tmp_path):
         assert len(open(cache).read().split()) > 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stack_placements_keep_bits(torch_cuda, tmp_path, prec):
+    """Every generic bucket forced (through tuner cache entries) to keep its
+    suffix stacks in LDS, in global memory, or none at all (suffix series
+    rebuilt where they are needed; windows >= 9 only) gives the bits of the
+    plan as built, and the forced stack-free buckets run as stack-free
+    launches (stage kind 6)."""
+    import ctypes
+    import math
+    import paper_2311_08595_amd as st
+    from paper_2311_08595_amd import _lib
+    torch = torch_cuda
+    w = wl.heavy_tail(seed=21, n=20000, m=200000)
+    r = w["r"]
+    xd = torch.tensor(w["x"], dtype=torch.float64, device="cuda")
+    with st.Plan(w["eptr"], w["eidx"], w["n"], r) as plan:
+        ref = plan.apply(xd, precision=prec).cpu().numpy()
+        bk, bm = plan.query(_lib.Q_BUCKET_K), plan.query(_lib.Q_BUCKET_M)
+    t = 0 if prec == "fp64" else 1
+    lib = _lib.load()
+    for place in (1, 0, 2):
+        cache = tmp_path / ("tune_%d.txt" % place)
+        with open(cache, "w") as f:
+            for k, m in zip(bk, bm):
+                if k >= 4:   # generic kernel everywhere, the given stack placement
+                    f.write("t%d_r%d_k%d_m%d %d %d %d\n" % (t, r, k, int(round(math.log2(max(1, m)))),
+                                                         0 if k <= 7 else -1, place, 0 if k <= 7 else -1))
+        with st.Plan(w["eptr"], w["eidx"], w["n"], r) as plan:
+            plan.autotune(xd, reps=1, cache_path=str(cache))
+            y = plan.apply(xd, precision=prec).cpu().numpy()
+            stacks = plan.query(_lib.Q_BUCKET_STACK)
+            cap = 256
+            ns = ctypes.c_int32()
+            kinds, sizes = (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)()
+            counts, ms = (ctypes.c_int64 * cap)(), (ctypes.c_float * cap)()
+            _lib.check(lib.sttsv_apply_timed(plan._h, ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(
+                torch.empty_like(xd).data_ptr()), _lib.PREC[prec], cap, ctypes.byref(ns), kinds, sizes, counts, ms))
+        assert y.tobytes() == ref.tobytes(), place
+        free = [int(k) for k, s_ in zip(bk, stacks) if int(s_) & (4 << t)]
+        _say(f"  {prec} placement {place}: stack-free buckets k={free}, kinds {sorted(set(kinds[:ns.value]))}")
+        if place == 2:
+            assert free and all(r - k + 1 >= 9 for k in free)
+            assert 6 in set(kinds[:ns.value])
+        else:
+            assert not free
+
+
 def test_compact_fp32_contributions_are_words(torch_cuda):
     """An FP32 apply stores every contribution as the upper 32 bits of its
     FP64 value, rounded to nearest: the contributions read back have zero low
@@ -401,9 +448,9 @@ def test_compact_fp32_contributions_are_words(torch_cuda):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_stage_list_covers_every_edge_once(torch_cuda, prec):
     """The launch sequence of an apply (per-bucket kernels, fused generic
-    launches with LDS or global-memory stacks, lane-group launches) processes
-    every edge exactly once, and the stack flags agree with the fused
-    launches' kinds."""
+    launches with LDS, global-memory or no suffix stacks, lane-group
+    launches) processes every edge exactly once, and the stack flags agree
+    with the fused launches' kinds."""
     import ctypes
     import paper_2311_08595_amd as st
     from paper_2311_08595_amd import _lib
@@ -421,7 +468,9 @@ def test_stage_list_covers_every_edge_once(torch_cuda, prec):
                                          _lib.PREC[prec], cap, ctypes.byref(ns), kinds, sizes, counts, ms))
         stacks = plan.query(_lib.Q_BUCKET_STACK)
         m = len(w["eptr"]) - 1
-        edge_stages = [(kinds[i], counts[i]) for i in range(ns.value) if kinds[i] in (0, 1, 4, 5)]
+        edge_stages = [(kinds[i], counts[i]) for i in range(ns.value) if kinds[i] in (0, 1, 4, 5, 6)]
     assert sum(c for _, c in edge_stages) == m
-    assert set(int(s) for s in stacks) <= {0, 1, 2, 3}
+    assert set(int(s) for s in stacks) <= set(range(16))
+    for s in stacks:                     # one placement per series type
+        assert not (int(s) & 1 and int(s) & 4) and not (int(s) & 2 and int(s) & 8)
     _say(f"  {prec}: stage kinds {sorted(set(k for k, _ in edge_stages))}")

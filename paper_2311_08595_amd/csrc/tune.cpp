@@ -123,18 +123,38 @@ float time_generic(Plan& p, Bucket& B, int t, int place, const EdgeCall& c, int 
 
 // Stream lanes by measurement: starting from the cost-model assignment, move
 // one edge stage at a time to another lane and keep the move when the whole
-// apply (median of reps, hipEvents on the plan's stream) gets faster by more
-// than 0.5 %; repeat while a round finds a move (at most four rounds).  The
-// lanes never change any bit of y.
+// apply gets faster by more than 0.5 %; repeat while a round finds a move (at
+// most four rounds).  A sample is kLaneBatch back-to-back applies (the steady
+// state of repeated applies, whose launches overlap across applies), timed
+// with hipEvents on the plan's stream; a candidate's time is the median of
+// max(reps, 5) samples.  The search's result is then timed against the
+// starting assignment in alternation and kept only if it wins, so timing
+// noise cannot leave a slower assignment than the cost model's.  The lanes
+// never change any bit of y.
+constexpr int kLaneBatch = 2;
 int tune_lanes(Plan& p, const double* x, int reps) {
   if ((p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr) return STTSV_OK;
   double* y = nullptr;
   if (hipMalloc(&y, sizeof(double) * static_cast<size_t>(p.n)) != hipSuccess) return STTSV_ENOMEM;
+  reps = std::max(reps, 5);
   for (int seq = 0; seq < 2; ++seq) {
     const int nl = p.lanes[seq];
     if (nl < 2) continue;
     const int prec = seq == 0 ? STTSV_PREC_FP64 : STTSV_PREC_FP32;
-    auto apply = [&] { return launch_sttsv(p, x, y, prec, nullptr, p.stream); };
+    auto apply = [&] {
+      hipError_t e = hipSuccess;
+      for (int q = 0; q < kLaneBatch && e == hipSuccess; ++q) e = launch_sttsv(p, x, y, prec, nullptr, p.stream);
+      return e;
+    };
+    auto lanes_now = [&] {
+      std::vector<int> v;
+      for (const Stage& S : p.stages[seq]) v.push_back(S.lane);
+      return v;
+    };
+    auto set_lanes = [&](const std::vector<int>& v) {
+      for (size_t i = 0; i < v.size(); ++i) p.stages[seq][i].lane = v[i];
+    };
+    const std::vector<int> start = lanes_now();
     float best = time_median(apply, reps, p.stream);
     for (int round = 0; round < 4; ++round) {
       bool moved = false;
@@ -154,6 +174,17 @@ int tune_lanes(Plan& p, const double* x, int reps) {
         }
       }
       if (!moved) break;
+    }
+    const std::vector<int> found = lanes_now();
+    if (found != start) {
+      float t_found = 0.f, t_start = 0.f;
+      for (int round = 0; round < 3; ++round) {
+        set_lanes(start);
+        t_start += time_median(apply, reps, p.stream);
+        set_lanes(found);
+        t_found += time_median(apply, reps, p.stream);
+      }
+      if (!(t_found < t_start)) set_lanes(start);
     }
   }
   const hipError_t e = hipStreamSynchronize(p.stream);

@@ -132,6 +132,7 @@ float time_generic(Plan& p, Bucket& B, int t, int place, const EdgeCall& c, int 
 // noise cannot leave a slower assignment than the cost model's.  The lanes
 // never change any bit of y.
 constexpr int kLaneBatch = 2;
+constexpr float kTuneMargin = 0.97f;   // a stack placement other than the default must be 3 % faster
 int tune_lanes(Plan& p, const double* x, int reps) {
   if ((p.flags & STTSV_FLAG_ONE_STREAM) || p.ev_fork == nullptr) return STTSV_OK;
   double* y = nullptr;
@@ -231,7 +232,15 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
         const float g_glb = time_generic(p, B, t, 0, c, reps);
         const float g_free = W >= kStackFreeMinW ? time_generic(p, B, t, kStackFree, c, reps) : 1e30f;
         const float g_best = std::min(g_lds, std::min(g_glb, g_free));
-        ch.lds = g_lds == g_best ? 1 : g_free == g_best ? kStackFree : 0;
+        // the planner's default placement unless another is clearly faster
+        // (near-ties would flip with timing noise from run to run)
+        const int tsz = t == 0 ? 8 : 4;
+        const bool def_lds = (int64_t)kGenBlock * kg_stack_bytes(B.k, W, tsz) <= kLdsBudget;
+        const float g_def = def_lds ? g_lds : g_glb;
+        if (g_best < kTuneMargin * g_def)
+          ch.lds = g_lds == g_best ? 1 : g_free == g_best ? kStackFree : 0;
+        else
+          ch.lds = def_lds ? 1 : 0;
         ch.use_kr = -1;
         if (kr != nullptr) {
           const BucketDesc d = B.desc[t];
@@ -252,7 +261,8 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
             ch.reuse = t_run < t_kr ? 1 : 0;
             t_kr = std::min(t_kr, t_run);
           }
-          ch.use_kr = t_kr <= g_best ? 1 : 0;
+          const float g_chosen = ch.lds == 1 ? g_lds : ch.lds == kStackFree ? g_free : g_glb;
+          ch.use_kr = t_kr <= g_chosen ? 1 : 0;
         }
         std::lock_guard<std::mutex> lk(g_mu);
         g_cache[key] = ch;

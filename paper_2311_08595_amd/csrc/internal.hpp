@@ -52,10 +52,13 @@ constexpr int64_t kg_stack_bytes(int k, int W, int tsz) {
   return 16LL * k + (int64_t)((k - 3 + kg_checkpoint(W, tsz) - 1) / kg_checkpoint(W, tsz)) * W * tsz;
 }
 // Stack-free generic variant (suffix series recomputed, scalars in LDS):
-// compiled for windows >= kStackFreeMinW only, where a suffix series is
-// long and k = r - W + 1 is small.
+// compiled for windows >= kStackFreeMinW, and for FP64 series up to
+// kStackFreeMaxW64 (its three live series fit the registers there without
+// scratch; longer FP64 windows would spill).
 constexpr int kStackFree = 2;
 constexpr int kStackFreeMinW = 9;
+constexpr int kStackFreeMaxW64 = 48;
+constexpr bool stack_free_ok(int W, int tsz) { return W >= kStackFreeMinW && (tsz == 4 || W <= kStackFreeMaxW64); }
 constexpr int64_t kg_scalar_bytes(int k) { return 16LL * k; }
 
 inline int gen_range_of(int W) {

@@ -660,7 +660,8 @@ int build_groups(Plan& P) {
           return (int64_t)kGenBlock * kg_stack_bytes(B.k, B.r - B.k + 1, static_cast<int>(tsz));
         };
         auto free_ok = [&](const Bucket& B) {   // the stack-free variant exists and its scalars fit
-          return B.r - B.k + 1 >= kStackFreeMinW && (int64_t)kGenBlock * kg_scalar_bytes(B.k) <= kLdsMax;
+          return stack_free_ok(B.r - B.k + 1, static_cast<int>(tsz)) &&
+                 (int64_t)kGenBlock * kg_scalar_bytes(B.k) <= kLdsMax;
         };
         // placement: 0 = stack in LDS, 1 = in global memory, 2 = no stack
         // (tuner choices; without one, LDS when it fits the default budget)

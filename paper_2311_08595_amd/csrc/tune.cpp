@@ -87,7 +87,7 @@ float time_generic(Plan& p, Bucket& B, int t, int place, const EdgeCall& c, int 
   const int64_t need = place == kStackFree ? (int64_t)kGenBlock * kg_scalar_bytes(B.k)
                                            : (int64_t)kGenBlock * kg_stack_bytes(B.k, W, tsz);
   if (place != 0 && need > kLdsMax) return 1e30f;
-  if (place == kStackFree && W < kStackFreeMinW) return 1e30f;
+  if (place == kStackFree && !stack_free_ok(W, tsz)) return 1e30f;
   BucketDesc d = B.desc[t];
   void* tmp = nullptr;
   d.lds_stack = place;
@@ -230,7 +230,7 @@ int autotune(Plan& p, const double* x, int reps, const char* cache_path, int32_t
       if (!cached) {
         const float g_lds = time_generic(p, B, t, 1, c, reps);
         const float g_glb = time_generic(p, B, t, 0, c, reps);
-        const float g_free = W >= kStackFreeMinW ? time_generic(p, B, t, kStackFree, c, reps) : 1e30f;
+        const float g_free = stack_free_ok(W, t == 0 ? 8 : 4) ? time_generic(p, B, t, kStackFree, c, reps) : 1e30f;
         const float g_best = std::min(g_lds, std::min(g_glb, g_free));
         // the planner's default placement unless another is clearly faster
         // (near-ties would flip with timing noise from run to run)

@@ -245,13 +245,18 @@ int zeigvec_sshopm(sttsv_plan_t plan, const double* x0, double alpha, double tol
 /*
  * sttsv_plan_autotune -- per size bucket and series type, time the kernel
  * variants that compute bitwise-identical contributions (register-resident
- * vs generic kernel for 4 <= |e| <= 7; suffix stack in LDS vs global memory
- * for the generic kernel) on the device and keep the fastest; then move the
- * edge launches between the stream lanes while whole applies get faster.
- * Tuning never changes any bit of y.
+ * vs generic kernel for 4 <= |e| <= 7; for the generic kernel, suffix stack
+ * in LDS, in global memory, or none with the suffix series rebuilt where
+ * they are needed, the last for windows r - |e| + 1 >= 9 (FP64: <= 48)) on
+ * the device and keep the fastest (a stack placement other than the
+ * planner's default only when it is 3 % faster); then move the edge launches
+ * between the stream lanes while whole applies get faster (samples of two
+ * applies; the result kept only if it beats the starting assignment when
+ * both are timed again in alternation).  Tuning never changes any bit of y.
  *   x           device, double[n]: a representative input (e.g. the start
  *               vector of a solve); only read.
- *   reps        >= 1 timed launches per candidate (median taken).
+ *   reps        >= 1 timed launches per candidate (median taken; at least 5
+ *               two-apply samples for the lane search).
  *   cache_path  host string or NULL: text file of earlier choices, keyed by
  *               (series type, r, |e|, round(log2 edges)); choices found there
  *               are applied without timing, new ones are appended.
